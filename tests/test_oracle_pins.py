@@ -1,0 +1,453 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: values
+worked by hand from the paper's definitions (tests/golden), closed forms,
+invariants, an independent library (numpy's Philox), exhaustive search, and a
+second, independent statement of the definitions (oracle/reference.py).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import reference
+from oracle.oracle import OracleProblem, candidate_matrix, count_stages, draw, philox4x64_10
+from oracle.oracle import stage_temperature, threshold
+from paper_2506_19866_amd import synth
+from tests.problems import from_edges, golden, random_problem
+
+
+# ---------------------------------------------------------------------------
+# Philox4x64-10 against numpy's independent implementation
+# ---------------------------------------------------------------------------
+def _numpy_block(counter, key):
+    """numpy pre-increments its 256-bit counter before producing a block, so
+    the block of counter c comes from a generator started at c - 1."""
+    c = sum(int(v) << (64 * i) for i, v in enumerate(counter))
+    c = (c - 1) % (1 << 256)
+    start = np.array([(c >> (64 * i)) & ((1 << 64) - 1) for i in range(4)], dtype=np.uint64)
+    bg = np.random.Philox(counter=start, key=np.array(key, dtype=np.uint64))
+    return bg.random_raw(4).astype(np.uint64)
+
+
+@pytest.mark.parametrize("counter,key", [
+    ((0, 0, 0, 0), (0, 0)),
+    ((1, 0, 0, 0), (0, 0)),
+    ((0, 5, 3, 0), (2003, 0)),          # step 0 of chain 5 of network 3
+    ((123456789, 17, 0, 0), (2003, 0)),
+    ((2**64 - 1, 2**64 - 1, 2**64 - 1, 2**64 - 1), (2**64 - 1, 2**64 - 1)),
+    ((0x243F6A8885A308D3, 0x13198A2E03707344, 0xA4093822299F31D0, 0x082EFA98EC4E6C89),
+     (0x452821E638D01377, 0xBE5466CF34E90C6C)),
+])
+def test_philox_matches_numpy(counter, key):
+    assert np.array_equal(philox4x64_10(counter, key), _numpy_block(counter, key))
+
+
+def test_draw_counter_layout():
+    # draw(seed, g, chain, net) is the block of counter (g, chain, net, 0), key (seed, 0)
+    assert np.array_equal(draw(7, 11, 3, 2), _numpy_block((11, 3, 2, 0), (7, 0)))
+
+
+# ---------------------------------------------------------------------------
+# hand-worked trajectories and costs (golden fixtures)
+# ---------------------------------------------------------------------------
+def _w1(step_size=1, theta=(0, 0, 0), n_steps=5, **kw):
+    g = golden("w1_three_node_loop.json")
+    edges = [(j, i) for j, i, _ in g["edges_src_dst_a"]]
+    prob, perm = from_edges(3, edges, init=g["init"], n_steps=n_steps, step_size=step_size, **kw)
+    x = np.zeros(6, dtype=np.int8)
+    for k, (_, _, a) in enumerate(g["edges_src_dst_a"]):
+        x[perm[k]] = a
+    x[3:] = theta
+    return g, prob, x
+
+
+def test_w1_canonical_order():
+    g, _, x = _w1()
+    assert x.tolist() == g["canonical_x"]
+
+
+@pytest.mark.parametrize("impl", ["c", "python"])
+def test_w1_trajectories(impl):
+    def sim(prob, x):
+        if impl == "c":
+            return OracleProblem(prob).simulate(x)[0].tolist()
+        return reference.simulate(prob, x)[0]
+    g, prob, x = _w1(step_size=1, n_steps=5)
+    assert sim(prob, x) == g["trajectory_d1"]
+    g, prob, x = _w1(step_size=2, n_steps=3)
+    assert sim(prob, x) == g["trajectory_d2"]
+    g, prob, x = _w1(step_size=1, theta=(0, 1, 0), n_steps=3)
+    assert sim(prob, x) == g["theta1_is_1_trajectory_d1"]
+
+
+@pytest.mark.parametrize("impl", ["c", "python"])
+def test_w1_cost(impl):
+    g = golden("w1_three_node_loop.json")
+    _, prob, x = _w1(n_steps=3, obs_t=g["obs_t"], obs_n=g["obs_n"], observed=[g["observed"]])
+    if impl == "c":
+        o = OracleProblem(prob)
+        got = (o.violations(x), o.mismatch(x), o.weight_sum(), o.penalty_weight(), o.cost(x))
+    else:
+        got = (reference.violations(prob, x), reference.mismatch(prob, x),
+               sum(map(sum, reference.weights(prob)[0])), reference.penalty_weight(prob),
+               reference.cost(prob, x))
+    assert got == (g["violations"], g["mismatch"], sum(map(sum, g["weights"])), g["lambda"], g["cost"])
+
+
+def test_w3_clamped_source_propagates():
+    g = golden("w3_clamped_chain.json")
+    edges = [(j, i) for j, i, _ in g["edges_src_dst_a"]]
+    prob, perm = from_edges(4, edges, init=g["init"], clamp=g["clamp"], n_steps=5)
+    x = np.zeros(3 + 4, dtype=np.int8)
+    for k, (_, _, a) in enumerate(g["edges_src_dst_a"]):
+        x[perm[k]] = a
+    traj = OracleProblem(prob).simulate(x)[0]
+    assert traj.tolist() == g["trajectory_d1"]
+    # the closed form of the fixture's citation
+    for m in range(1, 4):
+        for t in range(6):
+            assert traj[t, m] == min(max(t - m + 1, 0), 2)
+
+
+# ---------------------------------------------------------------------------
+# closed forms and invariants of the model (§2.1, §2.2, §2.5.3 b)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("step_size", [1, 2])
+def test_decay_to_zero_with_no_input(step_size):
+    """§2.5.3 b: with zero node bias and no active regulation every node
+    decays to 0: s(t) = max(s(0) - t, 0) for d = 1, and 0 from t = 1 for d = 2."""
+    prob, _ = random_problem(11, n_nodes=9, n_edges=30, n_cond=3, n_steps=6, n_times=2, n_obs=3,
+                             clamps=(0, 0), step_size=step_size)
+    x = np.zeros(prob["n_edges"] + prob["n_nodes"], dtype=np.int8)
+    traj = OracleProblem(prob).simulate(x)
+    s0 = prob["init"].astype(np.int64)
+    for t in range(prob["n_steps"] + 1):
+        expect = np.maximum(s0 - t, 0) if step_size == 1 else (s0 if t == 0 else 0 * s0)
+        assert np.array_equal(traj[:, t, :], expect)
+
+
+def test_positive_threshold_only_lowers():
+    """Raising theta_i can never raise node i at any time when all a >= 0."""
+    prob, _ = random_problem(12, n_nodes=8, n_edges=20, n_cond=2, n_steps=6, n_times=2, n_obs=3,
+                             clamps=(0, 0))
+    rng = np.random.default_rng(0)
+    o = OracleProblem(prob)
+    for _ in range(20):
+        x = synth.random_params(rng, 1, prob["n_edges"], prob["n_nodes"])[0]
+        x[:prob["n_edges"]] = np.abs(x[:prob["n_edges"]])
+        x[prob["n_edges"]:] = 0
+        hi = o.simulate(x)
+        x2 = x.copy()
+        x2[prob["n_edges"]:] = 2
+        lo = o.simulate(x2)
+        assert (lo <= hi).all()
+
+
+def test_clamped_nodes_hold():
+    prob, _ = random_problem(13, n_nodes=10, n_edges=35, n_cond=4, n_steps=8, n_times=2, n_obs=4,
+                             clamps=(1, 3))
+    rng = np.random.default_rng(1)
+    o = OracleProblem(prob)
+    for _ in range(10):
+        x = synth.random_params(rng, 1, prob["n_edges"], prob["n_nodes"])[0]
+        traj = o.simulate(x)
+        for c in range(prob["n_cond"]):
+            for i in np.flatnonzero(prob["clamp"][c] >= 0):
+                assert (traj[c, :, i] == prob["clamp"][c, i]).all()
+        assert traj.min() >= 0 and traj.max() <= 2
+
+
+def test_relabeling_invariance():
+    """Renaming nodes permutes trajectories and leaves costs unchanged."""
+    prob, _ = random_problem(14, n_nodes=9, n_edges=27, n_cond=3, n_steps=7, n_times=3, n_obs=4,
+                             clamps=(1, 1), noise=0.1)
+    N, E = prob["n_nodes"], prob["n_edges"]
+    rng = np.random.default_rng(2)
+    pi = rng.permutation(N)                       # old node v -> new node pi[v]
+    edges = [(int(prob["src"][e]), i) for i in range(N) for e in range(prob["row_ptr"][i], prob["row_ptr"][i + 1])]
+    new_edges = [(int(pi[j]), int(pi[i])) for j, i in edges]
+    init = np.empty_like(prob["init"]); init[:, pi] = prob["init"]
+    clamp = np.empty_like(prob["clamp"]); clamp[:, pi] = prob["clamp"]
+    obs_n_new = pi[prob["obs_n"]]
+    order = np.argsort(obs_n_new)
+    observed = prob["observed"][:, :, order]
+    prob2, perm = from_edges(N, new_edges, init=init, clamp=clamp, n_steps=prob["n_steps"],
+                             obs_t=prob["obs_t"], obs_n=obs_n_new[order], observed=observed)
+    o1, o2 = OracleProblem(prob), OracleProblem(prob2)
+    for _ in range(10):
+        x = synth.random_params(rng, 1, E, N)[0]
+        x2 = np.empty_like(x)
+        x2[perm] = x[:E]
+        x2[E + pi] = x[E:]
+        t1, t2 = o1.simulate(x), o2.simulate(x2)
+        assert np.array_equal(t2[:, :, pi], t1)
+        assert o1.cost(x) == o2.cost(x2)
+
+
+# ---------------------------------------------------------------------------
+# objective (§2.3) and constraints (§2.5.3)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name", ["c1", "c2", "c3"])
+def test_hidden_parameters_fit_clean_data_exactly(name):
+    """The reference data are trajectories of the hidden vector, so it scores
+    0 on the noise-free data (the paper reaches y = 0 on pseudo-data, §3.2)."""
+    w = synth.load_workload(name)
+    clean = dict(w, observed=w["clean"])
+    assert OracleProblem(clean).cost(w["hidden"]) == 0
+    assert OracleProblem(w).violations(w["hidden"]) == 0
+
+
+def test_self_consistent_data_zero_mismatch():
+    prob, _ = random_problem(15, n_nodes=10, n_edges=30, n_cond=3, n_steps=9, n_times=3, n_obs=5)
+    rng = np.random.default_rng(3)
+    for _ in range(10):
+        x = synth.random_params(rng, 1, prob["n_edges"], prob["n_nodes"])[0]
+        traj = OracleProblem(prob).simulate(x)
+        own = dict(prob, observed=traj[:, prob["obs_t"], :][:, :, prob["obs_n"]])
+        assert OracleProblem(own).mismatch(x) == 0
+
+
+def test_weighted_between_one_and_three_times_unweighted():
+    """W = |G| + 1 lies in {1,2,3}; the paper's fit has weighted 20 against
+    unweighted 14 (§3.1)."""
+    prob, _ = random_problem(16, n_nodes=12, n_edges=40, n_cond=4, n_steps=10, n_times=4, n_obs=6,
+                             noise=0.2)
+    o = OracleProblem(prob)
+    rng = np.random.default_rng(4)
+    for _ in range(20):
+        x = synth.random_params(rng, 1, prob["n_edges"], prob["n_nodes"])[0]
+        traj = o.simulate(x)
+        S = traj[:, prob["obs_t"], :][:, :, prob["obs_n"]].astype(int)
+        unweighted = int(np.abs(S - prob["observed"]).sum())
+        m = o.mismatch(x)
+        assert unweighted <= m <= 3 * unweighted
+
+
+def test_mismatch_additive_over_conditions():
+    prob, _ = random_problem(17, n_nodes=10, n_edges=30, n_cond=4, n_steps=8, n_times=3, n_obs=4,
+                             noise=0.2)
+    rng = np.random.default_rng(5)
+    x = synth.random_params(rng, 1, prob["n_edges"], prob["n_nodes"])[0]
+    total = OracleProblem(prob).mismatch(x)
+    parts = 0
+    for c in range(prob["n_cond"]):
+        sub = dict(prob, n_cond=1, init=prob["init"][c:c + 1], clamp=prob["clamp"][c:c + 1],
+                   observed=prob["observed"][c:c + 1])
+        parts += OracleProblem(sub).mismatch(x)
+    assert total == parts
+
+
+def test_single_flip_changes_mismatch_by_weight():
+    """Flipping one reference entry of a perfectly fitted vector costs exactly
+    the weight times the flip size (weights recomputed from the new data)."""
+    prob, hidden = random_problem(18, n_nodes=10, n_edges=30, n_cond=2, n_steps=8, n_times=1, n_obs=4)
+    R = prob["observed"].copy()
+    R[1, 0, 2] = (R[1, 0, 2] + 2) % 3
+    flipped = dict(prob, observed=R)
+    # with one observed time every weight is 1
+    assert OracleProblem(flipped).mismatch(hidden) == abs(int(R[1, 0, 2]) - int(prob["observed"][1, 0, 2]))
+
+
+def test_violation_counts():
+    prob, hidden = random_problem(19, n_nodes=10, n_edges=30, n_cond=2, n_steps=5, n_times=2, n_obs=3)
+    o = OracleProblem(prob)
+    N, E = prob["n_nodes"], prob["n_edges"]
+    assert o.violations(hidden) == 0
+    x = np.zeros(E + N, dtype=np.int8)
+    assert o.violations(x) == 2 * N                # no edge active at all
+    x[:E] = 1
+    assert o.violations(x) == 0                    # every edge activating
+    x[:E] = -1
+    assert o.violations(x) == N                    # non-zero out-edges, nothing activating
+    assert o.cost(x) == o.mismatch(x) + o.penalty_weight() * N
+    lam = o.penalty_weight()
+    assert lam == 1 + 2 * o.weight_sum()
+    assert lam > 2 * o.weight_sum()                # larger than any mismatch: |S-R| <= 2
+
+
+def test_feasible_generator_is_feasible():
+    w = synth.load_workload("c3")
+    o = OracleProblem(w)
+    for x in synth.feasible_params(np.random.default_rng(6), 16, w["row_ptr"], w["src"]):
+        assert o.violations(x) == 0
+
+
+# ---------------------------------------------------------------------------
+# exhaustive search and the independent Python statement
+# ---------------------------------------------------------------------------
+def _tiny(seed=21, noise=0.0, hard=1):
+    return random_problem(seed, n_nodes=3, n_edges=5, n_cond=2, n_steps=6, n_times=3, n_obs=2,
+                          noise=noise, clamps=(0, 1), hard=hard)
+
+
+def test_c_oracle_equals_python_statement_on_every_candidate():
+    prob, _ = _tiny(noise=0.3)
+    o = OracleProblem(prob)
+    X = candidate_matrix(o.n_params, o.n_edges)
+    costs_c = o.cost_batch(X)
+    costs_py = np.array([reference.cost(prob, x) for x in X])
+    assert np.array_equal(costs_c, costs_py)
+    best, argmin, nmin, all_costs = o.brute_force(with_costs=True)
+    assert np.array_equal(all_costs, costs_c)
+    assert best == costs_c.min() and nmin == int((costs_c == best).sum())
+    assert np.array_equal(argmin, X[int(np.argmin(costs_c))])
+
+
+def test_brute_force_finds_zero_on_clean_data():
+    prob, hidden = random_problem(22, n_nodes=4, n_edges=6, n_cond=2, n_steps=6, n_times=3, n_obs=3,
+                                  clamps=(1, 1))
+    o = OracleProblem(prob)
+    assert o.cost(hidden) == 0
+    best, argmin, nmin, _ = o.brute_force()
+    assert best == 0 and o.cost(argmin) == 0 and nmin >= 1
+
+
+# ---------------------------------------------------------------------------
+# schedule and fixed-point Metropolis threshold (§2.4.1, Table 1)
+# ---------------------------------------------------------------------------
+def test_paper_schedule_stage_count():
+    g = golden("paper_schedule.json")
+    n = count_stages(g["T0"], g["T_min"], g["rho"])
+    assert n == g["n_stages"]
+    assert n * g["n_iterations"] == g["steps_per_chain"]
+
+
+def test_stage_temperature_is_iterated_product():
+    T = 2.0
+    rho = synth.cooling_factor(2.0, 0.01, 100)
+    for k in range(100):
+        assert stage_temperature(2.0, rho, k) == T
+        T = T * rho
+    assert abs(stage_temperature(2.0, rho, 99) - 0.01) < 1e-12
+
+
+def test_threshold_definition_and_monotonicity():
+    for T in (0.01, 0.3, 1.0, 2.0, 50.0):
+        prev = 2**32
+        for d in range(1, 200):
+            t = threshold(T, d)
+            assert t == min(math.floor(math.ldexp(math.exp(-d / T), 32)), 2**32 - 1)
+            assert t <= prev
+            prev = t
+    for d in (1, 5, 40):
+        assert threshold(0.5, d) <= threshold(1.0, d) <= threshold(2.0, d)
+    assert threshold(1e-6, 1) == 0                 # greedy limit
+    assert threshold(1e12, 1) == 2**32 - 1         # accepts everything (clipped)
+
+
+def test_fixed_point_acceptance_frequency():
+    """Accepting when the top 32 bits of draw word 2 fall below the threshold
+    reproduces exp(-D/T) (binomial 5-sigma band over 20000 draws)."""
+    n = 20000
+    u = np.array([int(draw(99, g, 0, 0)[2]) >> 32 for g in range(n)])
+    for T, d in ((1.0, 1), (0.5, 1), (2.0, 3)):
+        p = math.exp(-d / T)
+        freq = float((u < threshold(T, d)).mean())
+        assert abs(freq - p) < 5 * math.sqrt(p * (1 - p) / n)
+
+
+def test_proposal_never_noop_and_uniform():
+    w = synth.load_workload("c1")
+    o = OracleProblem(w)
+    P, E = o.n_params, o.n_edges
+    x = synth.start_vectors("c1", w, 1)[0]
+    counts = np.zeros(P)
+    moves = {}
+    n = 40000
+    for g in range(n):
+        i, v = o.propose(x, draw(5, g, 0, 0))
+        assert 0 <= i < P and v != x[i]
+        assert (-1 <= v <= 1) if i < E else (0 <= v <= 2)
+        counts[i] += 1
+        moves[(i, v)] = moves.get((i, v), 0) + 1
+    chi2 = float(((counts - n / P) ** 2 / (n / P)).sum())
+    assert chi2 < P + 6 * math.sqrt(2 * P)
+    for i in range(P):
+        pair = [moves.get((i, v), 0) for v in (range(-1, 2) if i < E else range(3)) if v != x[i]]
+        assert abs(pair[0] - pair[1]) < 6 * math.sqrt(n / P)
+
+
+# ---------------------------------------------------------------------------
+# the annealing loop (Table 1)
+# ---------------------------------------------------------------------------
+def _run(prob, x0, **kw):
+    base = dict(seed=2001, T0=2.0, rho=0.9, n_stages=6, steps_per_stage=60)
+    base.update(kw)
+    return OracleProblem(prob).run(x0, **base)
+
+
+def test_run_invariants_and_thread_independence():
+    w = synth.load_workload("c1")
+    x0 = synth.start_vectors("c1", w, 12)
+    r1 = _run(w, x0, n_threads=1)
+    r3 = _run(w, x0, n_threads=3)
+    for k in r1:
+        assert np.array_equal(np.asarray(r1[k]), np.asarray(r3[k])), k
+    o = OracleProblem(w)
+    assert o.cost(r1["x"]) == r1["cost"] == r1["stage_best"][-1]
+    assert o.violations(r1["x"]) == 0
+    assert (np.diff(r1["stage_best"]) <= 0).all()
+    assert r1["stage_best"][0] <= o.cost_batch(x0).min()
+    cb = r1["chain_best"]
+    assert r1["winner"] == int(np.argmin(cb)) and cb.min() == r1["cost"]
+    for n in range(len(x0)):
+        assert o.cost(r1["chain_xbest"][n]) == cb[n]
+    L = 60
+    assert (r1["stage_accepted"] + r1["stage_infeasible"] <= len(x0) * L).all()
+    assert (r1["stage_uphill"] + r1["stage_neutral"] <= r1["stage_accepted"]).all()
+
+
+def test_resume_is_bit_identical():
+    w = synth.load_workload("c1")
+    x0 = synth.start_vectors("c1", w, 8)
+    full = _run(w, x0, n_stages=6)
+    head = _run(w, x0, n_stages=2)
+    tail = _run(w, np.repeat(head["x"][None, :], 8, axis=0), n_stages=4, first_stage=2)
+    assert np.array_equal(full["stage_best"], np.concatenate([head["stage_best"], tail["stage_best"]]))
+    assert np.array_equal(full["stage_accepted"][2:], tail["stage_accepted"])
+    assert np.array_equal(full["x"], tail["x"])
+
+
+def test_greedy_limit_never_goes_uphill():
+    w = synth.load_workload("c1")
+    x0 = synth.start_vectors("c1", w, 4)
+    r = _run(w, x0, T0=1e-9, rho=1.0, n_stages=3)
+    assert (r["stage_uphill"] == 0).all()
+
+
+def test_hot_limit_accepts_nearly_everything():
+    w = synth.load_workload("c1")
+    x0 = synth.start_vectors("c1", w, 4)
+    r = _run(w, x0, T0=1e9, rho=1.0, n_stages=2)
+    feasible_steps = 4 * 60 - r["stage_infeasible"]
+    assert (r["stage_accepted"] == feasible_steps).all()
+
+
+def test_penalty_mode_never_rejects_as_infeasible():
+    w = dict(synth.load_workload("c1"), hard=0)
+    x0 = synth.start_vectors("c1", w, 4)
+    r = _run(w, x0, n_stages=2)
+    assert (r["stage_infeasible"] == 0).all()
+
+
+def test_hard_mode_rejects_infeasible_start():
+    w = synth.load_workload("c1")
+    x0 = np.zeros((2, 40), dtype=np.int8)
+    with pytest.raises(ValueError):
+        _run(w, x0)
+
+
+def test_annealing_reaches_global_minimum_on_tiny_networks():
+    """Table 1 should find the exhaustive-search optimum on a tiny network for
+    most seeds (here: all of 5)."""
+    prob, _ = random_problem(23, n_nodes=4, n_edges=6, n_cond=2, n_steps=6, n_times=3, n_obs=3,
+                             clamps=(1, 1), noise=0.15)
+    o = OracleProblem(prob)
+    best, _, _, _ = o.brute_force()
+    x0 = synth.feasible_params(np.random.default_rng(7), 8, prob["row_ptr"], prob["src"])
+    hits = 0
+    for seed in range(5):
+        r = o.run(x0, seed=seed, T0=2.0, rho=0.9, n_stages=30, steps_per_stage=100)
+        hits += r["cost"] == best
+    assert hits >= 4
