@@ -1,0 +1,175 @@
+/*
+ * sa_anneal.h -- C ABI of the MI355X (gfx950) library that fits the ternary
+ * parameters of a discrete logic model of a regulatory network to sparse
+ * time-course data by massively parallel simulated annealing.
+ *
+ * Method: Reimer et al., "GPU-accelerated modeling of biological regulatory
+ * networks" (arXiv 2506.19866).
+ *   - model: §2.1 (states s in {0,1,2}; image K_i = sum over regulators of the
+ *     regulator terms) with the synchronous update named in §2.2; here the
+ *     term of edge j->i is a_ji * s_j with a in {-1,0,+1} (polarity times a
+ *     0/1 weight, threshold 1) and the node threshold theta_i in {0,1,2} is
+ *     subtracted from the image (theta = 0 is the zero node bias of §2.5.3 b);
+ *     a free node moves towards clamp(K_i, 0, 2) by at most d levels per step;
+ *   - objective: §2.3, the Manhattan distance between simulated and reference
+ *     data at the observed points, weighted by |G| + 1 where G is the
+ *     difference between consecutive observed time points (0 at the first);
+ *   - constraints: §2.5.3 (a) every node has a non-zero out-edge and (b) every
+ *     node has an activating (+1) in-edge; cost = M + lambda * V where V counts
+ *     the failing nodes of (a) plus those of (b);
+ *   - search: Table 1 (parallel simulated annealing with a global restart from
+ *     the best chain after every temperature stage).
+ *
+ * Conventions of every entry point:
+ *   - return 0 (SA_OK) on success, a negative SA_ERR_* code on failure; the
+ *     message of the last failure of the calling thread is sa_last_error();
+ *   - "host" pointers are read during the call only (the library copies what
+ *     it keeps); "device" pointers are HIP device memory owned by the caller
+ *     and must stay valid until the work queued on the given stream is done;
+ *   - `stream` is a hipStream_t (NULL = the default stream); calls that take a
+ *     stream only enqueue work on it, except where stated;
+ *   - objects returned through `out` are owned by the library and released by
+ *     the matching sa_destroy_* call; they may be used from one thread at a
+ *     time.
+ */
+#ifndef SA_ANNEAL_H
+#define SA_ANNEAL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SA_OK = 0,
+  SA_ERR_ARG = -1,         /* null pointer, size or count out of range */
+  SA_ERR_DOMAIN = -2,      /* a state, parameter or observation outside its domain */
+  SA_ERR_TOPOLOGY = -3,    /* malformed graph, or (hard mode) a node without in- or out-edges */
+  SA_ERR_INFEASIBLE = -4,  /* hard mode: a starting vector breaks a constraint */
+  SA_ERR_DEVICE = -5,      /* a HIP call failed */
+  SA_ERR_OOM = -6,         /* device allocation failed */
+  SA_ERR_UNSUPPORTED = -7, /* size beyond what the kernels handle (see sa_create_problem) */
+  SA_ERR_OVERFLOW = -8     /* the largest possible cost does not fit in int32 */
+};
+
+enum { SA_HARD = 0, SA_PENALTY = 1 };
+
+typedef struct sa_problem sa_problem;
+typedef struct sa_run sa_run;
+
+/* A network, its experimental conditions and the reference data (§2.3, §2.5).
+ * All pointers are host pointers, copied by sa_create_problem. */
+typedef struct {
+  int32_t n_nodes;            /* N >= 1 */
+  int32_t n_edges;            /* E >= 0 */
+  const int32_t *in_row_ptr;  /* [N+1]: in-edges of node i are in_row_ptr[i] .. in_row_ptr[i+1]-1;
+                                 this order is the canonical parameter order */
+  const int32_t *in_src;      /* [E]: source node, strictly ascending within a row, never the target */
+  int32_t n_conditions;       /* C >= 1 (initial states plus perturbations) */
+  const int8_t *init_state;   /* [C*N]: state at t = 0, in {0,1,2} */
+  const int8_t *clamp;        /* [C*N]: -1 = free, else the value the node is held at for all t */
+  int32_t n_steps;            /* T_s >= 1 synchronous update steps */
+  int32_t n_obs_times;        /* K >= 1 */
+  const int32_t *obs_times;   /* [K]: strictly increasing, in [0, T_s] */
+  int32_t n_obs_nodes;        /* O >= 1 */
+  const int32_t *obs_nodes;   /* [O]: distinct nodes */
+  const int8_t *observed;     /* [C*K*O]: reference data R, row-major (condition, time, node), in {0,1,2} */
+  int32_t step_size;          /* d in {1,2} */
+  int32_t constraint_mode;    /* SA_HARD: a proposal that breaks (a) or (b) is a rejected step (§2.5.3);
+                                 SA_PENALTY: every proposal is scored with lambda * V */
+  int32_t penalty;            /* lambda >= 0; 0 selects 1 + 2 * sum(W), larger than any mismatch */
+} sa_problem_desc;
+
+typedef struct {
+  int32_t n_params;   /* P = E + N: x = [a_e in in-CSR order] ++ [theta_0 .. theta_{N-1}] */
+  int32_t n_nodes, n_edges, n_conditions, n_steps, n_obs_times, n_obs_nodes;
+  int32_t weight_sum; /* sum of W over all observations */
+  int32_t penalty;    /* lambda in effect */
+  int32_t max_cost;   /* 2 * weight_sum + lambda * 2N */
+} sa_problem_info;
+
+/* Validates the description, precomputes the weights W and lambda and the
+ * register layout of the kernels, and copies everything to the current HIP
+ * device (synchronous).  Sizes handled: N <= 191, C <= 64.
+ * Errors: SA_ERR_ARG, SA_ERR_DOMAIN, SA_ERR_TOPOLOGY, SA_ERR_UNSUPPORTED,
+ * SA_ERR_OVERFLOW, SA_ERR_DEVICE, SA_ERR_OOM. */
+int sa_create_problem(const sa_problem_desc *desc, sa_problem **out);
+int sa_destroy_problem(sa_problem *prob);
+int sa_problem_get_info(const sa_problem *prob, sa_problem_info *info);
+
+/* cost_dev[i] = M(x_i) + lambda * V(x_i) (§2.3, §2.5.3) for the n vectors
+ * x_dev[i*P .. i*P+P-1] (device, int8, a in {-1,0,1}, theta in {0,1,2}).
+ * Values outside the domain are not checked (their cost is unspecified).
+ * n = 0 is a no-op. */
+int sa_eval_cost(const sa_problem *prob, const int8_t *x_dev, int64_t n, int32_t *cost_dev, void *stream);
+
+/* traj_dev[((i*C + c)*(T_s+1) + t)*N + v] = state of node v at step t under
+ * condition c for vector x_i (device, int8): the synchronous trajectories of
+ * §2.2, clamped nodes held.  n = 0 is a no-op. */
+int sa_simulate(const sa_problem *prob, const int8_t *x_dev, int64_t n, int8_t *traj_dev, void *stream);
+
+/* Annealing schedule and chains (Table 1).  Stage k runs at
+ * T_k = T0 * rho * rho * ... (k products, IEEE double) and accepts an uphill
+ * move of size D iff the top 32 bits of Philox word 2 are below
+ * floor(2^32 * exp(-D / T_k)) (clipped to 2^32 - 1).  Step `it` of stage k
+ * of chain n of problem p draws Philox4x64-10 with counter
+ * (k * steps_per_stage + it, n, p, 0) and key (seed, 0). */
+typedef struct {
+  int64_t n_chains;          /* chains per problem, >= 1 */
+  uint64_t seed;
+  double T0;                 /* > 0 */
+  double rho;                /* > 0 */
+  int32_t first_stage;       /* >= 0: stage index of the first stage (resume from a checkpoint) */
+  int32_t n_stages;          /* >= 0: stages in the schedule of this run */
+  int32_t steps_per_stage;   /* L >= 1 */
+} sa_run_desc;
+
+/* Per temperature stage, per problem (before the global restart). */
+typedef struct {
+  int32_t best_cost;         /* lowest chain-best cost */
+  int32_t winner;            /* its chain (lowest id on ties) */
+  uint64_t accepted;         /* accepted proposals, all chains */
+  uint64_t uphill;           /* accepted with D > 0 */
+  uint64_t neutral;          /* accepted with D = 0 */
+  uint64_t infeasible;       /* hard mode: proposals rejected for breaking (a) or (b) */
+} sa_stage_stats;
+
+/* Creates a run over n_probs problems (each with desc->n_chains chains) and
+ * queues nothing.  x0_dev (device, int8) holds every chain's starting vector,
+ * problems in order, [n_chains * P_p] each; it is copied.  In hard mode every
+ * starting vector must satisfy (a) and (b) (else SA_ERR_INFEASIBLE); checking
+ * that synchronises `stream`.  This version handles n_probs == 1. */
+int sa_run_create(sa_problem *const *probs, int32_t n_probs, const sa_run_desc *desc,
+                  const int8_t *x0_dev, sa_run **out, void *stream);
+
+/* Queues the next n_stages stages of the schedule (asynchronous).  The total
+ * over all calls may not exceed desc->n_stages. */
+int sa_run_launch(sa_run *run, int32_t n_stages, void *stream);
+
+/* sa_run_create followed by sa_run_launch of the whole schedule. */
+int sa_run_chains(sa_problem *const *probs, int32_t n_probs, const sa_run_desc *desc,
+                  const int8_t *x0_dev, sa_run **out, void *stream);
+
+/* Global best after the last launched stage: vector (host, [P]), its cost and
+ * the chain it came from.  Synchronises the run's stream.  Any output may be NULL. */
+int sa_best(sa_run *run, int32_t prob, int8_t *x_host, int32_t *cost, int32_t *winner_chain);
+
+/* Statistics of every launched stage (host, [stages launched]).  Synchronises. */
+int sa_stats(sa_run *run, int32_t prob, sa_stage_stats *stats_host);
+
+/* Every chain's best cost (host, [n_chains]) and vector (host, [n_chains*P])
+ * after the last launched stage, before the restart.  Synchronises.  Either
+ * output may be NULL. */
+int sa_chain_best(sa_run *run, int32_t prob, int32_t *cost_host, int8_t *x_host);
+
+int sa_destroy_run(sa_run *run);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char *sa_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SA_ANNEAL_H */

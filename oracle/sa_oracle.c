@@ -269,6 +269,7 @@ typedef struct {
   int32_t n_stages;
   int32_t steps_per_stage;
   int32_t n_threads;
+  int64_t first_chain;  /* Philox chain id of chain 0 (to recompute any subset of a larger run) */
 } ora_run_args;
 
 typedef struct {
@@ -294,7 +295,7 @@ static void *run_chains_of_stage(void *arg) {
     for (int64_t it = 0; it < L; ++it) {
       uint64_t g = (uint64_t)(w->stage * L + it);
       uint64_t u[4];
-      ora_draw(w->args->seed, g, (uint64_t)n, (uint64_t)w->args->net, u);
+      ora_draw(w->args->seed, g, (uint64_t)(w->args->first_chain + n), (uint64_t)w->args->net, u);
       int8_t nv;
       int64_t i = ora_propose(p, xc, u, &nv);
       memcpy(cand, xc, (size_t)P);

@@ -1,0 +1,93 @@
+// sa_internal.h -- device-side problem layout shared by the host part of the
+// library (sa_api.hip) and its kernels (sa_kernels.hip).  Not a public header.
+//
+// Register-resident simulation on the int8 matrix cores of gfx950
+// ---------------------------------------------------------------
+// One wavefront owns one chain.  The synchronous update of all nodes under 16
+// conditions at once is one product per time step,
+//     H[row(i)][c] = sum_j A[row(i)][col(j)] * S[col(j)][c],
+// where A holds the chain's edge values a_ji (and -theta_i in the column of a
+// constant "bias" input fixed at 1), and S the int8 states, one column per
+// condition.  It runs as v_mfma_i32_16x16x64_i8 tiles: A is the 16x64 A
+// operand of m-tile mt and k-tile kt, S the 64x16 B operand of k-tile kt.
+//
+// Lane l holds A rows l%16 and B/D columns l%16 (condition), and the k-range
+// of lane group g = l/16 (A and B share that k mapping).  The D result of
+// m-tile mt holds rows 4g + r (r = 0..3) in lane group g.  Each node gets one
+// "slot" (g, q): its state leaves the product in lane group g, m-tile q/4,
+// register r = q%4, and re-enters the next product as byte q%16 of k-tile
+// q/16 in the same lane group.  So the 4 results of m-tile mt pack into
+// exactly one dword of the next B operand (k-tile mt/4, dword mt%4) and the
+// whole trajectory stays in the lane's registers: no LDS, no cross-lane
+// traffic.
+#pragma once
+#include <stdint.h>
+
+namespace sa {
+
+constexpr int kWave = 64;
+constexpr int kMaxTilesM = 12;  // N <= 191: 12 m-tiles, 3 k-tiles of 64
+constexpr int kMaxCondGroups = 4;
+
+struct DevProblem {
+  int32_t N, E, P, C, T, K, O;
+  int32_t CG;      // condition groups of 16
+  int32_t nm, nk;  // m-tiles (16 rows) and k-tiles (64 columns)
+  int32_t nd;      // dwords per lane that hold observed slots
+  int32_t d;       // step size
+  int32_t hard;
+  int32_t lambda;
+  // [P]: lane | (register << 8) | (byte << 16) of the A entry of parameter p
+  const uint32_t *param_pos;
+  const int32_t *edge_src, *edge_dst;  // [E]
+  const int32_t *in_ptr;               // [N+1]
+  const int32_t *out_ptr, *out_eid;    // [N+1], [E]: out-edges of each node (edge ids)
+  // [CG][4*nk dwords][64 lanes]: initial packed states, clamp mask, clamp value
+  const uint32_t *b0, *cmask, *cval;
+  // [CG][K][nd dwords][64 lanes]: packed reference values and weights (0 where unobserved)
+  const uint32_t *obs_r, *obs_w;
+  const int32_t *obs_t;                // [K]
+  const int16_t *slot_node;            // [4][16*nk]: node at (g, q), -1 bias/empty
+};
+
+// One temperature stage of one problem.
+struct StageArgs {
+  int64_t n_chains;
+  uint64_t seed;
+  int32_t net;
+  int32_t stage;          // absolute stage index k
+  int32_t L;              // steps per stage
+  int32_t dcap;           // largest uphill move with a non-zero threshold
+  const uint32_t *tau;    // [dcap+1] thresholds of this stage (entry 0 unused)
+  const int8_t *x_start;  // first stage: [n_chains*P]; later: winner [P]
+  int64_t x_start_stride; // P or 0
+  int8_t *xbest;          // [n_chains*P] out
+  int32_t *cbest;         // [n_chains] out
+  uint32_t *cstats;       // [n_chains*4] out: accepted, uphill, neutral, infeasible
+};
+
+struct StageRecord {
+  int32_t best_cost;
+  int32_t winner;
+  uint64_t accepted, uphill, neutral, infeasible;
+};
+
+struct ReduceArgs {
+  int64_t n_chains;
+  int32_t P;
+  const int32_t *cbest;
+  const int8_t *xbest;
+  const uint32_t *cstats;
+  int8_t *xwin;           // [P] out
+  StageRecord *rec;       // this stage's record (out)
+};
+
+// Launch wrappers (sa_kernels.hip).  All return a hipError_t as int.
+int launch_eval(const DevProblem &pb, const int8_t *x, int64_t n, int32_t *cost, void *stream);
+int launch_simulate(const DevProblem &pb, const int8_t *x, int64_t n, int8_t *traj, void *stream);
+int launch_stage(const DevProblem &pb, const StageArgs &sa, void *stream);
+int launch_reduce(const ReduceArgs &ra, void *stream);
+size_t stage_smem_bytes(const DevProblem &pb, int waves_per_block);
+int stage_waves_per_block(const DevProblem &pb);
+
+}  // namespace sa

@@ -1,0 +1,252 @@
+"""Python binding of libsa_anneal.so (include/sa_anneal.h).
+
+Argument marshalling only: every step of the annealing, the simulation and
+the scoring runs in the library's HIP kernels.  torch supplies device memory
+and the current stream.  The binding refuses to run when the library is not
+built: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsa_anneal.so")
+
+SA_OK = 0
+SA_ERR_ARG, SA_ERR_DOMAIN, SA_ERR_TOPOLOGY, SA_ERR_INFEASIBLE = -1, -2, -3, -4
+SA_ERR_DEVICE, SA_ERR_OOM, SA_ERR_UNSUPPORTED, SA_ERR_OVERFLOW = -5, -6, -7, -8
+SA_HARD, SA_PENALTY = 0, 1
+
+EXPORTS = ("sa_create_problem", "sa_destroy_problem", "sa_problem_get_info", "sa_eval_cost",
+           "sa_simulate", "sa_run_create", "sa_run_launch", "sa_run_chains", "sa_best", "sa_stats",
+           "sa_chain_best", "sa_destroy_run", "sa_last_error")
+
+
+class SAError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"sa error {code}: {msg}")
+        self.code = code
+
+
+class _ProblemDesc(C.Structure):
+    _fields_ = [
+        ("n_nodes", C.c_int32), ("n_edges", C.c_int32),
+        ("in_row_ptr", C.c_void_p), ("in_src", C.c_void_p),
+        ("n_conditions", C.c_int32), ("init_state", C.c_void_p), ("clamp", C.c_void_p),
+        ("n_steps", C.c_int32),
+        ("n_obs_times", C.c_int32), ("obs_times", C.c_void_p),
+        ("n_obs_nodes", C.c_int32), ("obs_nodes", C.c_void_p),
+        ("observed", C.c_void_p),
+        ("step_size", C.c_int32), ("constraint_mode", C.c_int32), ("penalty", C.c_int32),
+    ]
+
+
+class _ProblemInfo(C.Structure):
+    _fields_ = [(k, C.c_int32) for k in (
+        "n_params", "n_nodes", "n_edges", "n_conditions", "n_steps", "n_obs_times", "n_obs_nodes",
+        "weight_sum", "penalty", "max_cost")]
+
+
+class _RunDesc(C.Structure):
+    _fields_ = [
+        ("n_chains", C.c_int64), ("seed", C.c_uint64), ("T0", C.c_double), ("rho", C.c_double),
+        ("first_stage", C.c_int32), ("n_stages", C.c_int32), ("steps_per_stage", C.c_int32),
+    ]
+
+
+class _StageStats(C.Structure):
+    _fields_ = [
+        ("best_cost", C.c_int32), ("winner", C.c_int32),
+        ("accepted", C.c_uint64), ("uphill", C.c_uint64), ("neutral", C.c_uint64),
+        ("infeasible", C.c_uint64),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Loads the built library (never builds it: run build() first)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise ImportError(f"{_LIB_PATH} is not built; run paper_2506_19866_amd.build.build()")
+        L = C.CDLL(_LIB_PATH)
+        vp = C.c_void_p
+        L.sa_create_problem.argtypes = [C.POINTER(_ProblemDesc), C.POINTER(vp)]
+        L.sa_destroy_problem.argtypes = [vp]
+        L.sa_problem_get_info.argtypes = [vp, C.POINTER(_ProblemInfo)]
+        L.sa_eval_cost.argtypes = [vp, vp, C.c_int64, vp, vp]
+        L.sa_simulate.argtypes = [vp, vp, C.c_int64, vp, vp]
+        L.sa_run_create.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(_RunDesc), vp, C.POINTER(vp), vp]
+        L.sa_run_launch.argtypes = [vp, C.c_int32, vp]
+        L.sa_run_chains.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(_RunDesc), vp, C.POINTER(vp), vp]
+        L.sa_best.argtypes = [vp, C.c_int32, vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.sa_stats.argtypes = [vp, C.c_int32, vp]
+        L.sa_chain_best.argtypes = [vp, C.c_int32, vp, vp]
+        L.sa_destroy_run.argtypes = [vp]
+        L.sa_last_error.restype = C.c_char_p
+        for name in EXPORTS:
+            if name != "sa_last_error":
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int) -> None:
+    if rc != SA_OK:
+        raise SAError(rc, lib().sa_last_error().decode())
+
+
+def _stream_handle(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _device_tensor(t, dtype, shape_last=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if shape_last is not None and (t.dim() != 2 or t.shape[1] != shape_last):
+        raise ValueError(f"expected shape [n, {shape_last}], got {tuple(t.shape)}")
+    return t
+
+
+class Problem:
+    """A network with its conditions and reference data (problem dict layout of
+    paper_2506_19866_amd.synth), staged on the current HIP device."""
+
+    def __init__(self, prob: dict, *, constraint_mode: int | None = None, penalty: int | None = None):
+        self._arrays = {
+            "row_ptr": np.ascontiguousarray(prob["row_ptr"], dtype=np.int32),
+            "src": np.ascontiguousarray(prob["src"], dtype=np.int32),
+            "init": np.ascontiguousarray(prob["init"], dtype=np.int8).reshape(-1),
+            "clamp": np.ascontiguousarray(prob["clamp"], dtype=np.int8).reshape(-1),
+            "obs_t": np.ascontiguousarray(prob["obs_t"], dtype=np.int32),
+            "obs_n": np.ascontiguousarray(prob["obs_n"], dtype=np.int32),
+            "observed": np.ascontiguousarray(prob["observed"], dtype=np.int8).reshape(-1),
+        }
+        a = self._arrays
+        mode = constraint_mode if constraint_mode is not None else (SA_HARD if int(prob.get("hard", 1)) else SA_PENALTY)
+        lam = int(penalty if penalty is not None else prob.get("penalty", 0))
+        d = _ProblemDesc(
+            int(prob["n_nodes"]), int(prob["n_edges"]), a["row_ptr"].ctypes.data,
+            a["src"].ctypes.data if len(a["src"]) else None,
+            int(prob["n_cond"]), a["init"].ctypes.data, a["clamp"].ctypes.data, int(prob["n_steps"]),
+            len(a["obs_t"]), a["obs_t"].ctypes.data, len(a["obs_n"]), a["obs_n"].ctypes.data,
+            a["observed"].ctypes.data, int(prob.get("step_size", 1)), mode, lam)
+        h = C.c_void_p()
+        _check(lib().sa_create_problem(C.byref(d), C.byref(h)))
+        self._h = h
+        info = _ProblemInfo()
+        _check(lib().sa_problem_get_info(h, C.byref(info)))
+        self.info = {k: getattr(info, k) for k, _ in _ProblemInfo._fields_}
+        self.n_params = info.n_params
+        self.n_nodes = info.n_nodes
+        self.n_cond = info.n_conditions
+        self.n_steps = info.n_steps
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sa_destroy_problem(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def eval_cost(self, x, out=None, stream=None):
+        """x: int8 CUDA tensor [n, P] -> int32 CUDA tensor [n] (asynchronous)."""
+        import torch
+        x = _device_tensor(x, torch.int8, self.n_params)
+        n = x.shape[0]
+        if out is None:
+            out = torch.empty(n, dtype=torch.int32, device=x.device)
+        _device_tensor(out, torch.int32)
+        _check(lib().sa_eval_cost(self._h, C.c_void_p(x.data_ptr()), n, C.c_void_p(out.data_ptr()),
+                                  _stream_handle(stream)))
+        return out
+
+    def simulate(self, x, out=None, stream=None):
+        """x: int8 CUDA tensor [n, P] -> int8 CUDA tensor [n, C, T_s+1, N]."""
+        import torch
+        x = _device_tensor(x, torch.int8, self.n_params)
+        n = x.shape[0]
+        if out is None:
+            out = torch.empty((n, self.n_cond, self.n_steps + 1, self.n_nodes), dtype=torch.int8, device=x.device)
+        _device_tensor(out, torch.int8)
+        _check(lib().sa_simulate(self._h, C.c_void_p(x.data_ptr()), n, C.c_void_p(out.data_ptr()),
+                                 _stream_handle(stream)))
+        return out
+
+
+class Run:
+    """Parallel annealing of one problem (Table 1).  create=True only sets the
+    run up; launch(k) queues the next k stages."""
+
+    def __init__(self, problem: Problem, x0, *, seed: int, T0: float, rho: float, n_stages: int,
+                 steps_per_stage: int, first_stage: int = 0, stream=None, launch: bool = True):
+        import torch
+        x0 = _device_tensor(x0, torch.int8, problem.n_params)
+        self.problem = problem
+        self.n_chains = x0.shape[0]
+        self.n_stages = n_stages
+        self.launched = 0
+        d = _RunDesc(self.n_chains, int(seed) & (2**64 - 1), float(T0), float(rho), int(first_stage),
+                     int(n_stages), int(steps_per_stage))
+        self._x0 = x0
+        probs = (C.c_void_p * 1)(problem.handle)
+        h = C.c_void_p()
+        _check(lib().sa_run_create(probs, 1, C.byref(d), C.c_void_p(x0.data_ptr()), C.byref(h),
+                                   _stream_handle(stream)))
+        self._h = h
+        if launch:
+            self.launch(n_stages, stream=stream)
+
+    def launch(self, n_stages: int, stream=None):
+        _check(lib().sa_run_launch(self._h, int(n_stages), _stream_handle(stream)))
+        self.launched += n_stages
+
+    def best(self):
+        x = np.zeros(self.problem.n_params, dtype=np.int8)
+        cost, winner = C.c_int32(), C.c_int32()
+        _check(lib().sa_best(self._h, 0, x.ctypes.data, C.byref(cost), C.byref(winner)))
+        return x, cost.value, winner.value
+
+    def stats(self) -> dict:
+        arr = (_StageStats * max(self.launched, 1))()
+        _check(lib().sa_stats(self._h, 0, C.cast(arr, C.c_void_p)))
+        out = {k: np.array([getattr(arr[i], k) for i in range(self.launched)],
+                           dtype=np.int64 if k in ("best_cost", "winner") else np.uint64)
+               for k, _ in _StageStats._fields_}
+        return out
+
+    def chain_best(self):
+        cost = np.zeros(self.n_chains, dtype=np.int32)
+        x = np.zeros((self.n_chains, self.problem.n_params), dtype=np.int8)
+        _check(lib().sa_chain_best(self._h, 0, cost.ctypes.data, x.ctypes.data))
+        return cost, x
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sa_destroy_run(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
