@@ -1,0 +1,182 @@
+#!/usr/bin/env python3
+"""Benchmark: simulated-annealing chain-steps per second on the 723-parameter
+(Mtb-scale) workload, one MI355X.
+
+A step is one temperature stage of Table 1 over the whole workload: every one
+of the 16384 chains runs 500 proposal/simulation/score/Metropolis steps, then
+the global restart from the best chain.  --steps K times K consecutive stages
+of the workload's schedule from its first stage (K = 200 is the complete
+schedule); --warmup W stages run first on a separate, discarded run.
+
+Prints ONE JSON line on stdout (progress goes to stderr).  The roofline figure
+is for the stage kernel, timed with HIP events recorded by the library on the
+launch stream; the CPU baseline is the oracle timed on a bounded sample of the
+same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# chip constants (MI355X): 256 CUs x 4 SIMDs x 16 lanes of 32-bit integer ALU at 2.4 GHz
+CU, SIMD_PER_CU, LANES, CLOCK_HZ = 256, 4, 16, 2.4e9
+ALU_PEAK_OPS = CU * SIMD_PER_CU * LANES * CLOCK_HZ          # 39.3e12 int32 lane-ops/s
+PROFILES = os.path.join(ROOT, "profiles")
+STAGE_KERNEL_SOURCES = ("paper_2506_19866_amd/csrc/sa_k_stage.hip", "paper_2506_19866_amd/csrc/sa_device.h",
+                        "paper_2506_19866_amd/csrc/sa_internal.h")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def stage_kernel_hash() -> str:
+    h = hashlib.sha256()
+    for rel in STAGE_KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_alu_ops(prob: dict) -> int:
+    """Integer operations per full simulation of one candidate that must go
+    through the vector ALU whatever unit does the regulator contraction:
+    per (condition, step, node) update 2 ops (bound the image to {0,1,2},
+    move towards it), per observation term 2 ops (|S - R|, weighted add)."""
+    C, T, N = prob["n_cond"], prob["n_steps"], prob["n_nodes"]
+    K, O = len(prob["obs_t"]), len(prob["obs_n"])
+    return 2 * C * T * N + 2 * C * K * O
+
+
+def traffic_from_profiles(launch_key: str):
+    """HBM bytes per stage-kernel launch from the committed PMC summary, or
+    None when it is missing or the kernel sources changed since."""
+    path = os.path.join(PROFILES, "stage_kernel_c3_pmc.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_sources_sha256_16") != stage_kernel_hash() or rec.get("launch") != launch_key:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(name: str, prob: dict, sched: dict, target_s: float) -> dict:
+    from oracle.oracle import OracleProblem
+    from paper_2506_19866_amd import synth
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    o = OracleProblem(prob)
+    L = sched["steps_per_stage"]
+    probe_chains, probe_steps = threads, 20
+    x = synth.start_vectors(name, prob, probe_chains)
+    t0 = time.perf_counter()
+    o.run(x, seed=sched["seed"], T0=sched["T0"], rho=sched["rho"], n_stages=1,
+          steps_per_stage=probe_steps, n_threads=threads)
+    rate = probe_chains * probe_steps / (time.perf_counter() - t0)
+    chains = max(threads, int(rate * target_s / L) // threads * threads)
+    x = synth.start_vectors(name, prob, chains)
+    t0 = time.perf_counter()
+    o.run(x, seed=sched["seed"], T0=sched["T0"], rho=sched["rho"], n_stages=1,
+          steps_per_stage=L, n_threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": chains * L / dt, "unit": "chain-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{name} stage 0 of its schedule: {chains} chains x {L} steps "
+                      f"({chains * L} chain-steps, {dt:.1f} s, {threads} threads, serial C oracle per chain)"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200, help="timed temperature stages")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed stages on a discarded run")
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU (asked for {max(args.gpus, world)}): the multi-GPU path is "
+              "a design (one all-reduce of the 64-bit best key per stage), not a build", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2506_19866_amd import sa, synth
+
+    name = args.workload
+    prob = synth.load_workload(name)
+    sched = synth.bench_schedule(name)
+    n, L = sched["n_chains"], sched["steps_per_stage"]
+    log(f"[bench] workload {name}: N={prob['n_nodes']} E={prob['n_edges']} "
+        f"P={prob['n_nodes'] + prob['n_edges']} C={prob['n_cond']} chains={n} L={L}")
+    x0 = torch.from_numpy(synth.start_vectors(name, prob, n)).cuda()
+    P = sa.Problem(prob)
+    torch.cuda.synchronize()
+
+    if args.warmup > 0:
+        warm = sa.Run(P, x0, seed=sched["seed"] + 1, T0=sched["T0"], rho=sched["rho"],
+                      n_stages=args.warmup, steps_per_stage=L)
+        warm.best()
+        warm.close()
+        log(f"[bench] warmup: {args.warmup} stages done")
+
+    run = sa.Run(P, x0, seed=sched["seed"], T0=sched["T0"], rho=sched["rho"], n_stages=args.steps,
+                 steps_per_stage=L, launch=False, record_times=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run.launch(args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stats = run.stats()
+    stage_ms = run.stage_times_ms()
+    _, best_cost, _ = run.best()
+    chain_steps = n * L * args.steps
+    value = chain_steps / elapsed
+    log(f"[bench] {args.steps} stages in {elapsed:.3f} s: {value:.4g} chain-steps/s, "
+        f"best cost {best_cost} (stage 0 best {int(stats['best_cost'][0])})")
+
+    # roofline of the stage kernel: algorithmic ALU work of the simulations it
+    # ran (one per feasible proposal plus one per chain at stage start)
+    per_sim = algorithmic_alu_ops(prob)
+    sims = (n * L - stats["infeasible"].astype(np.float64)) + n
+    ops_per_launch = float(np.mean(sims)) * per_sim
+    avg_launch_s = float(np.mean(stage_ms)) * 1e-3
+    achieved = ops_per_launch / avg_launch_s
+    launch_key = f"{name}:{n}x{L}"
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK_OPS / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / ALU_PEAK_OPS, "traffic": traffic_from_profiles(launch_key),
+                "kernel": "stage_kernel<8,2,1>", "avg_launch_ms": float(np.mean(stage_ms)),
+                "ops_per_launch": ops_per_launch}
+    out = {
+        "metric": "SA chain-steps/s at 723-param scale", "value": value, "unit": "chain-steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int8",
+        "data": "synthetic (seeded generator + oracle-simulated reference data, stored workload)",
+        "config": {"workload": f"{name}: Mtb-scale, {prob['n_nodes']} nodes, {prob['n_edges']} edges, "
+                               f"{prob['n_nodes'] + prob['n_edges']} ternary params, {prob['n_cond']} conditions, "
+                               f"{prob['n_steps']} steps; {n} chains x {L} steps per stage, "
+                               f"{args.steps} stages of a {sched['n_stages']}-stage schedule T0={sched['T0']}",
+                   "chains": n, "steps_per_stage": L, "stages_timed": args.steps,
+                   "best_cost": int(best_cost)},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a bounded sample ...")
+        out["cpu_baseline"] = cpu_baseline(name, prob, sched, args.cpu_seconds)
+        log(f"[bench] cpu baseline: {out['cpu_baseline']['value']:.4g} chain-steps/s "
+            f"on {out['cpu_baseline']['cores']} threads")
+    print(json.dumps(out), flush=True)
+    run.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -123,6 +123,7 @@ typedef struct {
   int32_t first_stage;       /* >= 0: stage index of the first stage (resume from a checkpoint) */
   int32_t n_stages;          /* >= 0: stages in the schedule of this run */
   int32_t steps_per_stage;   /* L >= 1 */
+  int32_t record_times;      /* non-zero: time every stage kernel with a HIP event pair on the launch stream */
 } sa_run_desc;
 
 /* Per temperature stage, per problem (before the global restart). */
@@ -162,6 +163,10 @@ int sa_stats(sa_run *run, int32_t prob, sa_stage_stats *stats_host);
  * after the last launched stage, before the restart.  Synchronises.  Either
  * output may be NULL. */
 int sa_chain_best(sa_run *run, int32_t prob, int32_t *cost_host, int8_t *x_host);
+
+/* Duration in milliseconds of the stage kernel of every launched stage
+ * (host, [stages launched]); needs desc->record_times.  Synchronises. */
+int sa_stage_times(sa_run *run, int32_t prob, float *ms_host);
 
 int sa_destroy_run(sa_run *run);
 

@@ -69,6 +69,7 @@ struct sa_run {
   std::vector<int32_t> dcap;
   int32_t launched = 0;
   hipStream_t stream = nullptr;
+  std::vector<hipEvent_t> ev_start, ev_stop;  // per stage, when record_times is set
 };
 
 extern "C" const char *sa_last_error(void) { return g_err.c_str(); }
@@ -381,6 +382,8 @@ static void tau_table(double T, int32_t max_delta, std::vector<uint32_t> &tab, i
 }
 
 static void free_run(sa_run *r) {
+  for (hipEvent_t e : r->ev_start) hipEventDestroy(e);
+  for (hipEvent_t e : r->ev_stop) hipEventDestroy(e);
   hipFree(r->x0);
   hipFree(r->xbest);
   hipFree(r->xwin);
@@ -449,6 +452,13 @@ extern "C" int sa_run_create(sa_problem *const *probs, int32_t n_probs, const sa
   alloc((void **)&r->cstats, (size_t)n * 16);
   alloc((void **)&r->tau, all_tau.size() * 4);
   alloc((void **)&r->rec, (size_t)std::max(S, 1) * sizeof(sa::StageRecord));
+  for (int st = 0; st < S && desc->record_times && e == hipSuccess; ++st) {
+    hipEvent_t a = nullptr, b = nullptr;
+    e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    r->ev_start.push_back(a);
+    r->ev_stop.push_back(b);
+  }
   if (e == hipSuccess) e = hipMemcpyAsync(r->x0, x0_dev, (size_t)(n * P), hipMemcpyDeviceToDevice, s);
   if (e == hipSuccess && !all_tau.empty())
     e = hipMemcpyAsync(r->tau, all_tau.data(), all_tau.size() * 4, hipMemcpyHostToDevice, s);
@@ -501,7 +511,10 @@ extern "C" int sa_run_launch(sa_run *r, int32_t n_stages, void *stream) {
     a.xbest = r->xbest;
     a.cbest = r->cbest;
     a.cstats = r->cstats;
+    const bool timed = !r->ev_start.empty();
+    if (timed) SA_HIP(hipEventRecord(r->ev_start[st], (hipStream_t)stream), "event record");
     SA_HIP((hipError_t)sa::launch_stage(pb, a, stream), "stage launch");
+    if (timed) SA_HIP(hipEventRecord(r->ev_stop[st], (hipStream_t)stream), "event record");
     sa::ReduceArgs ra{};
     ra.n_chains = r->desc.n_chains;
     ra.P = P;
@@ -575,6 +588,16 @@ extern "C" int sa_chain_best(sa_run *r, int32_t prob, int32_t *cost, int8_t *x_h
   if (cost) SA_HIP(hipMemcpy(cost, r->cbest, (size_t)n * 4, hipMemcpyDeviceToHost), "copy chain costs");
   if (x_host)
     SA_HIP(hipMemcpy(x_host, r->xbest, (size_t)(n * r->prob->dev.P), hipMemcpyDeviceToHost), "copy chain bests");
+  return SA_OK;
+}
+
+extern "C" int sa_stage_times(sa_run *r, int32_t prob, float *ms) {
+  int rc = sync_run(r, prob);
+  if (rc != SA_OK) return rc;
+  if (!ms) return fail(SA_ERR_ARG, "out is NULL");
+  if (r->ev_start.empty()) return fail(SA_ERR_ARG, "run was created without record_times");
+  for (int32_t i = 0; i < r->launched; ++i)
+    SA_HIP(hipEventElapsedTime(&ms[i], r->ev_start[i], r->ev_stop[i]), "event elapsed");
   return SA_OK;
 }
 

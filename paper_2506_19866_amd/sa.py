@@ -21,7 +21,7 @@ SA_HARD, SA_PENALTY = 0, 1
 
 EXPORTS = ("sa_create_problem", "sa_destroy_problem", "sa_problem_get_info", "sa_eval_cost",
            "sa_simulate", "sa_run_create", "sa_run_launch", "sa_run_chains", "sa_best", "sa_stats",
-           "sa_chain_best", "sa_destroy_run", "sa_last_error")
+           "sa_chain_best", "sa_stage_times", "sa_destroy_run", "sa_last_error")
 
 
 class SAError(RuntimeError):
@@ -53,6 +53,7 @@ class _RunDesc(C.Structure):
     _fields_ = [
         ("n_chains", C.c_int64), ("seed", C.c_uint64), ("T0", C.c_double), ("rho", C.c_double),
         ("first_stage", C.c_int32), ("n_stages", C.c_int32), ("steps_per_stage", C.c_int32),
+        ("record_times", C.c_int32),
     ]
 
 
@@ -86,6 +87,7 @@ def lib():
         L.sa_best.argtypes = [vp, C.c_int32, vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.sa_stats.argtypes = [vp, C.c_int32, vp]
         L.sa_chain_best.argtypes = [vp, C.c_int32, vp, vp]
+        L.sa_stage_times.argtypes = [vp, C.c_int32, vp]
         L.sa_destroy_run.argtypes = [vp]
         L.sa_last_error.restype = C.c_char_p
         for name in EXPORTS:
@@ -198,7 +200,8 @@ class Run:
     run up; launch(k) queues the next k stages."""
 
     def __init__(self, problem: Problem, x0, *, seed: int, T0: float, rho: float, n_stages: int,
-                 steps_per_stage: int, first_stage: int = 0, stream=None, launch: bool = True):
+                 steps_per_stage: int, first_stage: int = 0, stream=None, launch: bool = True,
+                 record_times: bool = False):
         import torch
         x0 = _device_tensor(x0, torch.int8, problem.n_params)
         self.problem = problem
@@ -206,7 +209,7 @@ class Run:
         self.n_stages = n_stages
         self.launched = 0
         d = _RunDesc(self.n_chains, int(seed) & (2**64 - 1), float(T0), float(rho), int(first_stage),
-                     int(n_stages), int(steps_per_stage))
+                     int(n_stages), int(steps_per_stage), 1 if record_times else 0)
         self._x0 = x0
         probs = (C.c_void_p * 1)(problem.handle)
         h = C.c_void_p()
@@ -239,6 +242,12 @@ class Run:
         x = np.zeros((self.n_chains, self.problem.n_params), dtype=np.int8)
         _check(lib().sa_chain_best(self._h, 0, cost.ctypes.data, x.ctypes.data))
         return cost, x
+
+    def stage_times_ms(self) -> np.ndarray:
+        """Stage-kernel durations (HIP events on the launch stream)."""
+        ms = np.zeros(max(self.launched, 1), dtype=np.float32)
+        _check(lib().sa_stage_times(self._h, 0, ms.ctypes.data))
+        return ms[:self.launched]
 
     def close(self):
         if getattr(self, "_h", None):
