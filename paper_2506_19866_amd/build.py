@@ -23,6 +23,8 @@ FLAGS = [
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core results go straight to VGPRs (no accumulation-register reads)
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wno-unused-result",
 ]
 

@@ -209,27 +209,25 @@ extern "C" int sa_create_problem(const sa_problem_desc *d, sa_problem **out) {
     for (int e = 0; e < E; ++e) out_eid[fill[esrc[e]]++] = e;
   }
 
-  // per (condition group, dword, lane): initial states, clamp mask and value
+  // per (condition group, dword, lane): initial states and the held-byte mask
   const int Q4 = 4 * nk;
-  std::vector<uint32_t> b0((size_t)CG * Q4 * 64), cm((size_t)CG * Q4 * 64), cv((size_t)CG * Q4 * 64);
+  std::vector<uint32_t> b0((size_t)CG * Q4 * 64), cm((size_t)CG * Q4 * 64);
   std::vector<uint32_t> orr((size_t)CG * K * nd * 64, 0), ow((size_t)CG * K * nd * 64, 0);
   for (int cg = 0; cg < CG; ++cg)
     for (int lane = 0; lane < 64; ++lane) {
       const int c = cg * 16 + lane % 16, g = lane / 16;
       for (int q4 = 0; q4 < Q4; ++q4) {
-        uint32_t vb = 0, vm = 0, vv = 0;
+        uint32_t vb = 0, vm = 0;
         for (int b = 0; b < 4; ++b) {
           const int q = q4 * 4 + b;
           const int v = slot_node[(size_t)g * slots + q];
-          int val = 0, held = 1, hv = 0;
+          int val = 0, held = 1;
           if (c < C && g == gb && q == qb) {
-            val = 1;
-            hv = 1;  // constant bias input
+            val = 1;  // constant bias input
           } else if (c < C && v >= 0) {
             const int cl = d->clamp[(size_t)c * N + v];
             if (cl >= 0) {
               val = cl;
-              hv = cl;
             } else {
               val = d->init_state[(size_t)c * N + v];
               held = 0;
@@ -237,12 +235,10 @@ extern "C" int sa_create_problem(const sa_problem_desc *d, sa_problem **out) {
           }
           vb |= (uint32_t)val << (8 * b);
           vm |= (held ? 0xffu : 0u) << (8 * b);
-          vv |= (uint32_t)hv << (8 * b);
         }
         const size_t at = ((size_t)cg * Q4 + q4) * 64 + lane;
         b0[at] = vb;
         cm[at] = vm;
-        cv[at] = vv;
       }
       if (c >= C) continue;
       for (int k = 0; k < K; ++k)
@@ -268,7 +264,7 @@ extern "C" int sa_create_problem(const sa_problem_desc *d, sa_problem **out) {
   const size_t o_esrc = lay.take((size_t)E * 4), o_edst = lay.take((size_t)E * 4);
   const size_t o_inptr = lay.take((size_t)(N + 1) * 4), o_outptr = lay.take((size_t)(N + 1) * 4);
   const size_t o_outeid = lay.take((size_t)E * 4);
-  const size_t o_b0 = lay.take(b0.size() * 4), o_cm = lay.take(cm.size() * 4), o_cv = lay.take(cv.size() * 4);
+  const size_t o_b0 = lay.take(b0.size() * 4), o_cm = lay.take(cm.size() * 4);
   const size_t o_or = lay.take(orr.size() * 4), o_ow = lay.take(ow.size() * 4);
   const size_t o_obst = lay.take((size_t)K * 4), o_slot = lay.take(slot_node.size() * 2);
   hipError_t e = hipMalloc(&pr->dmem, lay.bytes);
@@ -289,7 +285,6 @@ extern "C" int sa_create_problem(const sa_problem_desc *d, sa_problem **out) {
   put(o_outeid, out_eid.data(), (size_t)E * 4);
   put(o_b0, b0.data(), b0.size() * 4);
   put(o_cm, cm.data(), cm.size() * 4);
-  put(o_cv, cv.data(), cv.size() * 4);
   put(o_or, orr.data(), orr.size() * 4);
   put(o_ow, ow.data(), ow.size() * 4);
   put(o_obst, d->obs_times, (size_t)K * 4);
@@ -315,7 +310,6 @@ extern "C" int sa_create_problem(const sa_problem_desc *d, sa_problem **out) {
   dp.out_eid = (const int32_t *)(base + o_outeid);
   dp.b0 = (const uint32_t *)(base + o_b0);
   dp.cmask = (const uint32_t *)(base + o_cm);
-  dp.cval = (const uint32_t *)(base + o_cv);
   dp.obs_r = (const uint32_t *)(base + o_or);
   dp.obs_w = (const uint32_t *)(base + o_ow);
   dp.obs_t = (const int32_t *)(base + o_obst);

@@ -195,23 +195,27 @@ __device__ __forceinline__ void build_a(ATile<NM, NK> &A, const DevProblem &pb, 
 // node update and score on packed states (4 conditions' bytes per dword)
 // ---------------------------------------------------------------------------
 // Packs clamp(t, 0, 2) of the four results of an m-tile into bytes: the
-// image bounded by the state range (§2.1, §2.2).
+// image bounded by the state range (§2.1, §2.2).  v_perm_b32 takes bytes 0-3
+// from its second operand and 4-7 from its first; 0x0c yields a zero byte.
 __device__ __forceinline__ uint32_t pack_targets(v4i acc) {
   const uint32_t k0 = (uint32_t)min(max(acc[0], 0), 2);
   const uint32_t k1 = (uint32_t)min(max(acc[1], 0), 2);
   const uint32_t k2 = (uint32_t)min(max(acc[2], 0), 2);
   const uint32_t k3 = (uint32_t)min(max(acc[3], 0), 2);
-  return k0 | (k1 << 8) | (k2 << 16) | (k3 << 24);
+  const uint32_t lo = __builtin_amdgcn_perm(k1, k0, 0x0c0c0400u);  // [k0, k1, 0, 0]
+  const uint32_t hi = __builtin_amdgcn_perm(k3, k2, 0x04000c0cu);  // [0, 0, k2, k3]
+  return lo | hi;
 }
 
-// d = 1: every byte moves one level towards its target.  With thermometer
-// bits (x>=1, x>=2) of the old state s and the target k:
-//   new >= 1  <=>  k >= 1 or s >= 2,     new >= 2  <=>  s >= 1 and k >= 2,
-// and new = [new >= 1] + [new >= 2].
+// d = 1: every byte moves one level towards its target, s' = s + sgn(k - s).
+// Over s, k in {0,1,2} the index s + 2k in [0, 6] determines s' uniquely:
+// index 0 1 2 3 4 5 6 -> 0 0 1 1 1 2 2 (pairs sharing an index agree, e.g.
+// (s,k) = (2,0) and (0,1) both give 1), so the update is one byte lookup
+// per condition, four per v_perm_b32.  k = s yields s (index 3s), which is
+// how clamped bytes are held.
 __device__ __forceinline__ uint32_t step_one_level(uint32_t k, uint32_t s) {
-  const uint32_t k2 = (k >> 1) & kLowBits, k1 = (k & kLowBits) | k2;
-  const uint32_t s2 = (s >> 1) & kLowBits, s1 = (s & kLowBits) | s2;
-  return (k1 | s2) + (s1 & k2);
+  const uint32_t idx = (k << 1) + s;  // bytes <= 6: no carries between bytes
+  return __builtin_amdgcn_perm(0x00020201u, 0x01010000u, idx);
 }
 
 // Weighted Manhattan distance of the packed states against the reference:
@@ -255,59 +259,75 @@ __device__ __forceinline__ void write_states(const v4i (&B)[NK], const DevProble
 // returns this lane's share of the mismatch M (§2.3).  Synchronous update of
 // §2.2: every m-tile of step t reads only the states of step t-1 (B) and
 // writes the states of step t (NB).  obs_r/obs_w: [CG][K][nd][64] tables.
+// One synchronous time step (§2.2): every m-tile reads only the states of
+// step t-1 (B) and writes those of step t (NB).  Clamped bytes (mask CM) get
+// their old state as target, so they hold.
+template <int NM, int NK, int D>
+__device__ __forceinline__ void time_step(const ATile<NM, NK> &A, const v4i (&B)[NK], v4i (&NB)[NK],
+                                          const v4i (&CM)[NK]) {
+  static_for<NM>([&](auto mtc) SA_INLINE {
+    constexpr int mt = decltype(mtc)::value;
+    v4i acc = {0, 0, 0, 0};
+    static_for<NK>([&](auto ktc) SA_INLINE {
+      constexpr int kt = decltype(ktc)::value;
+      acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(afrag<mt, kt>(A), B[kt], acc, 0, 0, 0);
+    });
+    const uint32_t s = (uint32_t)B[mt >> 2][mt & 3];
+    const uint32_t cm = (uint32_t)CM[mt >> 2][mt & 3];
+    const uint32_t k = pack_targets(acc);
+    const uint32_t target = k ^ ((k ^ s) & cm);  // cm ? s : k, one 3-input bit operation
+    NB[mt >> 2][mt & 3] = (int)(D == 1 ? step_one_level(target, s) : target);
+  });
+  // dwords without an m-tile (slots beyond the rows) carry over unchanged
+  static_for<4 * NK>([&](auto qc) SA_INLINE {
+    constexpr int q = decltype(qc)::value;
+    if constexpr (q >= NM) NB[q >> 2][q & 3] = B[q >> 2][q & 3];
+  });
+}
+
+// Simulates every condition for the chain whose parameters are in A and
+// returns this lane's share of the mismatch M (§2.3).  obs_r/obs_w:
+// [CG][K][nd][64] tables.  The two state buffers alternate between steps.
 template <int NM, int NK, int D, bool TRAJ>
 __device__ __forceinline__ int lane_mismatch(const ATile<NM, NK> &A, const DevProblem &pb, int lane,
                                              const uint32_t *obs_r, const uint32_t *obs_w,
                                              int8_t *__restrict__ traj) {
   int total = 0;
   for (int cg = 0; cg < pb.CG; ++cg) {
-    v4i B[NK], CM[NK], CV[NK];
+    v4i B0[NK], B1[NK], CM[NK];
     const int base = cg * 4 * NK;
 #pragma unroll
     for (int kt = 0; kt < NK; ++kt)
 #pragma unroll
       for (int dw = 0; dw < 4; ++dw) {
         const int at = (base + kt * 4 + dw) * kWave + lane;
-        B[kt][dw] = (int)pb.b0[at];
+        B0[kt][dw] = (int)pb.b0[at];
         CM[kt][dw] = (int)pb.cmask[at];
-        CV[kt][dw] = (int)pb.cval[at];
       }
     const int c = cg * 16 + (lane & 15);
     const uint32_t *rbase = obs_r + (size_t)cg * pb.K * pb.nd * kWave;
     const uint32_t *wbase = obs_w + (size_t)cg * pb.K * pb.nd * kWave;
     int k = 0;
     int tnext = pb.obs_t[0];
-    if (TRAJ) write_states<NK>(B, pb, lane, c, 0, traj);
-    if (tnext == 0) {
-      total += score<NK>(B, rbase, wbase, pb.nd, lane);
-      k = 1;
-      tnext = k < pb.K ? pb.obs_t[k] : -1;
-    }
-    for (int t = 1; t <= pb.T; ++t) {
-      v4i NB[NK];
-#pragma unroll
-      for (int kt = 0; kt < NK; ++kt) NB[kt] = B[kt];
-      static_for<NM>([&](auto mtc) SA_INLINE {
-        constexpr int mt = decltype(mtc)::value;
-        v4i acc = {0, 0, 0, 0};
-        static_for<NK>([&](auto ktc) SA_INLINE {
-          constexpr int kt = decltype(ktc)::value;
-          acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(afrag<mt, kt>(A), B[kt], acc, 0, 0, 0);
-        });
-        const uint32_t target = pack_targets(acc);
-        const uint32_t s = (uint32_t)B[mt >> 2][mt & 3];
-        const uint32_t moved = D == 1 ? step_one_level(target, s) : target;
-        const uint32_t cm = (uint32_t)CM[mt >> 2][mt & 3];
-        NB[mt >> 2][mt & 3] = (int)((moved & ~cm) | (uint32_t)CV[mt >> 2][mt & 3]);
-      });
-#pragma unroll
-      for (int kt = 0; kt < NK; ++kt) B[kt] = NB[kt];
+    auto observe = [&](const v4i (&B)[NK], int t) SA_INLINE {
       if (TRAJ) write_states<NK>(B, pb, lane, c, t, traj);
       if (t == tnext) {
         total += score<NK>(B, rbase + (size_t)k * pb.nd * kWave, wbase + (size_t)k * pb.nd * kWave, pb.nd, lane);
         ++k;
         tnext = k < pb.K ? pb.obs_t[k] : -1;
       }
+    };
+    observe(B0, 0);
+    int t = 1;
+    for (; t + 1 <= pb.T; t += 2) {
+      time_step<NM, NK, D>(A, B0, B1, CM);
+      observe(B1, t);
+      time_step<NM, NK, D>(A, B1, B0, CM);
+      observe(B0, t + 1);
+    }
+    if (t <= pb.T) {
+      time_step<NM, NK, D>(A, B0, B1, CM);
+      observe(B1, t);
     }
   }
   return total;

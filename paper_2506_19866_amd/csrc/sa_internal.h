@@ -1,5 +1,5 @@
 // sa_internal.h -- device-side problem layout shared by the host part of the
-// library (sa_api.hip) and its kernels (sa_kernels.hip).  Not a public header.
+// library (sa_api.hip) and its kernels (sa_k_batch.hip, sa_k_stage.hip).  Not a public header.
 //
 // Register-resident simulation on the int8 matrix cores of gfx950
 // ---------------------------------------------------------------
@@ -42,8 +42,10 @@ struct DevProblem {
   const int32_t *edge_src, *edge_dst;  // [E]
   const int32_t *in_ptr;               // [N+1]
   const int32_t *out_ptr, *out_eid;    // [N+1], [E]: out-edges of each node (edge ids)
-  // [CG][4*nk dwords][64 lanes]: initial packed states, clamp mask, clamp value
-  const uint32_t *b0, *cmask, *cval;
+  // [CG][4*nk dwords][64 lanes]: packed states at t = 0 (clamped nodes at
+  // their clamp value) and the mask of bytes that are held (clamped nodes,
+  // the bias slot, empty slots and lanes beyond the last condition)
+  const uint32_t *b0, *cmask;
   // [CG][K][nd dwords][64 lanes]: packed reference values and weights (0 where unobserved)
   const uint32_t *obs_r, *obs_w;
   const int32_t *obs_t;                // [K]
@@ -82,7 +84,7 @@ struct ReduceArgs {
   StageRecord *rec;       // this stage's record (out)
 };
 
-// Launch wrappers (sa_kernels.hip).  All return a hipError_t as int.
+// Launch wrappers (sa_k_batch.hip, sa_k_stage.hip).  All return a hipError_t as int.
 int launch_eval(const DevProblem &pb, const int8_t *x, int64_t n, int32_t *cost, void *stream);
 int launch_simulate(const DevProblem &pb, const int8_t *x, int64_t n, int8_t *traj, void *stream);
 int launch_stage(const DevProblem &pb, const StageArgs &sa, void *stream);
