@@ -124,7 +124,23 @@ typedef struct {
   int32_t n_stages;          /* >= 0: stages in the schedule of this run */
   int32_t steps_per_stage;   /* L >= 1 */
   int32_t record_times;      /* non-zero: time every stage kernel with a HIP event pair on the launch stream */
+  int32_t kernel;            /* SA_KERNEL_AUTO: the register layout specialised to the network for one
+                                problem, the many-network persistent kernel for several;
+                                SA_KERNEL_PERSISTENT: the persistent kernel also for one problem */
+  int32_t chains_per_block;  /* persistent kernel: chains per work item / workgroup, 1, 2, 4 or 8;
+                                0 = autotune (times the first stage with each, keeps the fastest) */
+  int32_t use_graph;         /* non-zero: every sa_run_launch call becomes one captured hipGraph launch;
+                                excludes record_times */
 } sa_run_desc;
+
+enum { SA_KERNEL_AUTO = 0, SA_KERNEL_PERSISTENT = 1 };
+
+typedef struct {
+  int32_t n_probs;
+  int32_t kernel;            /* SA_KERNEL_PERSISTENT when the many-network kernel runs */
+  int32_t chains_per_block;  /* as chosen (by the autotuner when asked) */
+  int32_t stages_launched;
+} sa_run_info;
 
 /* Per temperature stage, per problem (before the global restart). */
 typedef struct {
@@ -136,11 +152,15 @@ typedef struct {
   uint64_t infeasible;       /* hard mode: proposals rejected for breaking (a) or (b) */
 } sa_stage_stats;
 
-/* Creates a run over n_probs problems (each with desc->n_chains chains) and
- * queues nothing.  x0_dev (device, int8) holds every chain's starting vector,
- * problems in order, [n_chains * P_p] each; it is copied.  In hard mode every
- * starting vector must satisfy (a) and (b) (else SA_ERR_INFEASIBLE); checking
- * that synchronises `stream`.  This version handles n_probs == 1. */
+/* Creates a run over n_probs independent problems (each with desc->n_chains
+ * chains) and queues nothing.  x0_dev (device, int8) holds every chain's
+ * starting vector, problems in order, [n_chains * P_p] each; it is copied.  In
+ * hard mode every starting vector must satisfy (a) and (b) (else
+ * SA_ERR_INFEASIBLE); checking that synchronises `stream`.  Several problems
+ * (or desc->kernel = SA_KERNEL_PERSISTENT) run in one persistent launch per
+ * stage and step size, networks up to 159 nodes; problem p draws its Philox
+ * blocks with network id p.  Autotuning (chains_per_block = 0) runs the first
+ * stage once per candidate before returning; results do not depend on it. */
 int sa_run_create(sa_problem *const *probs, int32_t n_probs, const sa_run_desc *desc,
                   const int8_t *x0_dev, sa_run **out, void *stream);
 
@@ -155,6 +175,9 @@ int sa_run_chains(sa_problem *const *probs, int32_t n_probs, const sa_run_desc *
 /* Global best after the last launched stage: vector (host, [P]), its cost and
  * the chain it came from.  Synchronises the run's stream.  Any output may be NULL. */
 int sa_best(sa_run *run, int32_t prob, int8_t *x_host, int32_t *cost, int32_t *winner_chain);
+
+/* Kernel choices of a run (no synchronisation). */
+int sa_run_get_info(sa_run *run, sa_run_info *info);
 
 /* Statistics of every launched stage (host, [stages launched]).  Synchronises. */
 int sa_stats(sa_run *run, int32_t prob, sa_stage_stats *stats_host);

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsa_anneal.so")
-SOURCES = ["sa_api.hip", "sa_k_batch.hip", "sa_k_stage.hip"]
+SOURCES = ["sa_api.hip", "sa_k_batch.hip", "sa_k_stage.hip", "sa_k_persist.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -58,18 +58,31 @@ struct sa_problem {
 };
 
 struct sa_run {
-  sa_problem *prob = nullptr;
+  std::vector<sa_problem *> probs;
   sa_run_desc desc{};
   int device = 0;
+  int64_t n = 0;                 // chains per problem
+  bool persistent = false;       // many-network kernel (else the specialised one)
+  int waves = 4;                 // chains per work item (persistent kernel)
+  int cus = 256;
+  int blocks_per_cu = 1;
+  std::vector<int64_t> x_off, w_off;
+  std::vector<int> item_class_begin, item_class_count, item_class_d;  // per step-size class
+  size_t smem = 0;
   int8_t *x0 = nullptr, *xbest = nullptr, *xwin = nullptr;
   int32_t *cbest = nullptr;
-  uint32_t *cstats = nullptr, *tau = nullptr;
-  sa::StageRecord *rec = nullptr;
+  uint32_t *cstats = nullptr, *tau = nullptr, *queue = nullptr;
+  sa::StageRecord *rec = nullptr;  // [n_stages][n_probs]
+  sa::DevProblem *probs_dev = nullptr;
+  int64_t *x_off_dev = nullptr, *w_off_dev = nullptr;
+  int32_t *item_net = nullptr, *item_chain0 = nullptr;
   std::vector<size_t> tau_off;
   std::vector<int32_t> dcap;
   int32_t launched = 0;
   hipStream_t stream = nullptr;
   std::vector<hipEvent_t> ev_start, ev_stop;  // per stage, when record_times is set
+  std::vector<hipGraphExec_t> graphs;
+  hipStream_t capture_stream = nullptr;  // private stream the stages are captured on
 };
 
 extern "C" const char *sa_last_error(void) { return g_err.c_str(); }
@@ -189,8 +202,8 @@ extern "C" int sa_create_problem(const sa_problem_desc *d, sa_problem **out) {
   auto place = [&](int p, int i, int colg, int colq) {
     const int lane = (4 * sg[i] + sq[i] % 4) + 16 * colg;
     const int mt = sq[i] / 4, kt = colq / 16, dw = (colq % 16) / 4, b = colq % 4;
-    const int reg = (mt * nk + kt) * 4 + dw;
-    param_pos[p] = (uint32_t)lane | ((uint32_t)reg << 8) | ((uint32_t)b << 16);
+    param_pos[p] = (uint32_t)lane | ((uint32_t)mt << 8) | ((uint32_t)kt << 12) | ((uint32_t)dw << 14) |
+                   ((uint32_t)b << 16);
   };
   for (int i = 0; i < N; ++i)
     for (int e = d->in_row_ptr[i]; e < d->in_row_ptr[i + 1]; ++e) {
@@ -378,14 +391,174 @@ static void tau_table(double T, int32_t max_delta, std::vector<uint32_t> &tab, i
 static void free_run(sa_run *r) {
   for (hipEvent_t e : r->ev_start) hipEventDestroy(e);
   for (hipEvent_t e : r->ev_stop) hipEventDestroy(e);
+  for (hipGraphExec_t g : r->graphs) hipGraphExecDestroy(g);
+  if (r->capture_stream) hipStreamDestroy(r->capture_stream);
   hipFree(r->x0);
   hipFree(r->xbest);
   hipFree(r->xwin);
   hipFree(r->cbest);
   hipFree(r->cstats);
   hipFree(r->tau);
+  hipFree(r->queue);
   hipFree(r->rec);
+  hipFree(r->probs_dev);
+  hipFree(r->x_off_dev);
+  hipFree(r->w_off_dev);
+  hipFree(r->item_net);
+  hipFree(r->item_chain0);
   delete r;
+}
+
+// Work items of the persistent kernel: (network, first chain) with `waves`
+// chains each, grouped by step size, longest networks first (per-step work
+// ~ C * T_s * m-tiles * k-tiles).  Returns the item count.
+static int build_items(sa_run *r, int waves, std::vector<int32_t> &net, std::vector<int32_t> &chain0) {
+  net.clear();
+  chain0.clear();
+  r->item_class_begin.clear();
+  r->item_class_count.clear();
+  r->item_class_d.clear();
+  const int np = (int)r->probs.size();
+  for (int d = 1; d <= 2; ++d) {
+    std::vector<int> order;
+    for (int i = 0; i < np; ++i)
+      if (r->probs[i]->dev.d == d) order.push_back(i);
+    if (order.empty()) continue;
+    auto work = [&](int i) {
+      const sa::DevProblem &p = r->probs[i]->dev;
+      return (long long)p.C * p.T * p.nm * p.nk;
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
+    r->item_class_begin.push_back((int)net.size());
+    r->item_class_d.push_back(d);
+    for (int i : order)
+      for (int64_t c = 0; c < r->n; c += waves) {
+        net.push_back(i);
+        chain0.push_back((int32_t)c);
+      }
+    r->item_class_count.push_back((int)net.size() - r->item_class_begin.back());
+  }
+  return (int)net.size();
+}
+
+static int upload_items(sa_run *r, int waves) {
+  std::vector<int32_t> net, chain0;
+  build_items(r, waves, net, chain0);
+  SA_HIP(hipMemcpy(r->item_net, net.data(), net.size() * 4, hipMemcpyHostToDevice), "copy items");
+  SA_HIP(hipMemcpy(r->item_chain0, chain0.data(), chain0.size() * 4, hipMemcpyHostToDevice), "copy items");
+  size_t smem = 0;
+  for (sa_problem *p : r->probs) smem = std::max(smem, sa::persistent_smem_bytes(p->dev, waves));
+  r->smem = smem;
+  r->waves = waves;
+  r->blocks_per_cu = sa::persistent_blocks_per_cu(waves, smem);
+  return SA_OK;
+}
+
+// Queues stage `st` (index within the run) on `stream`.
+static int enqueue_stage(sa_run *r, int32_t st, hipStream_t stream) {
+  const int np = (int)r->probs.size();
+  const bool first = st == 0;
+  const bool timed = !r->ev_start.empty();
+  if (timed) SA_HIP(hipEventRecord(r->ev_start[st], stream), "event record");
+  if (!r->persistent) {
+    const sa::DevProblem &pb = r->probs[0]->dev;
+    sa::StageArgs a{};
+    a.n_chains = r->n;
+    a.seed = r->desc.seed;
+    a.net = 0;
+    a.stage = r->desc.first_stage + st;
+    a.L = r->desc.steps_per_stage;
+    a.dcap = r->dcap[st];
+    a.tau = r->tau + r->tau_off[st];
+    a.x_start = first ? r->x0 : r->xwin;
+    a.x_start_stride = first ? pb.P : 0;
+    a.xbest = r->xbest;
+    a.cbest = r->cbest;
+    a.cstats = r->cstats;
+    SA_HIP((hipError_t)sa::launch_stage(pb, a, stream), "stage launch");
+  } else {
+    for (size_t k = 0; k < r->item_class_d.size(); ++k) {
+      sa::BatchArgs a{};
+      a.probs = r->probs_dev;
+      a.n_probs = np;
+      a.n_chains = r->n;
+      a.item_net = r->item_net + r->item_class_begin[k];
+      a.item_chain0 = r->item_chain0 + r->item_class_begin[k];
+      a.n_items = r->item_class_count[k];
+      a.waves = r->waves;
+      a.queue = r->queue + k;
+      a.seed = r->desc.seed;
+      a.stage = r->desc.first_stage + st;
+      a.L = r->desc.steps_per_stage;
+      a.dcap = r->dcap[st];
+      a.tau = r->tau + r->tau_off[st];
+      a.x_start = first ? r->x0 : r->xwin;
+      a.first = first;
+      a.x_off = r->x_off_dev;
+      a.w_off = r->w_off_dev;
+      a.xbest = r->xbest;
+      a.cbest = r->cbest;
+      a.cstats = r->cstats;
+      const int grid = std::max(1, std::min(a.n_items, r->cus * r->blocks_per_cu));
+      SA_HIP((hipError_t)sa::launch_persistent(a, r->item_class_d[k], grid, r->smem, stream), "persistent launch");
+    }
+  }
+  if (timed) SA_HIP(hipEventRecord(r->ev_stop[st], stream), "event record");
+  sa::BatchReduceArgs ra{};
+  ra.n_probs = np;
+  ra.n_chains = r->n;
+  ra.probs = r->probs_dev;
+  ra.x_off = r->x_off_dev;
+  ra.w_off = r->w_off_dev;
+  ra.cbest = r->cbest;
+  ra.xbest = r->xbest;
+  ra.cstats = r->cstats;
+  ra.xwin = r->xwin;
+  ra.rec = r->rec + (size_t)st * np;
+  ra.queue = r->persistent ? r->queue : nullptr;
+  SA_HIP((hipError_t)sa::launch_batch_reduce(ra, stream), "reduce launch");
+  return SA_OK;
+}
+
+// Chains per work item for the persistent kernel: the candidate that runs the
+// first stage fastest.  Re-running that stage only rewrites its outputs.
+static int autotune_waves(sa_run *r, hipStream_t s) {
+  const int candidates[] = {1, 2, 4, 8};
+  float best_ms = 0.f;
+  int best = 4;
+  hipEvent_t e0, e1;
+  SA_HIP(hipEventCreate(&e0), "event");
+  SA_HIP(hipEventCreate(&e1), "event");
+  int rc = SA_OK;
+  for (int w : candidates) {
+    if ((rc = upload_items(r, w)) != SA_OK) break;
+    hipError_t e = hipMemsetAsync(r->queue, 0, 2 * sizeof(uint32_t), s);
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    if (e != hipSuccess) {
+      rc = hip_fail(e, "autotune");
+      break;
+    }
+    if ((rc = enqueue_stage(r, 0, s)) != SA_OK) break;
+    float ms = 0.f;
+    e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) {
+      rc = hip_fail(e, "autotune");
+      break;
+    }
+    if (best_ms == 0.f || ms < best_ms) {
+      best_ms = ms;
+      best = w;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc != SA_OK) return rc;
+  rc = upload_items(r, best);
+  if (rc != SA_OK) return rc;
+  SA_HIP(hipMemsetAsync(r->queue, 0, 2 * sizeof(uint32_t), s), "queue reset");
+  return SA_OK;
 }
 
 extern "C" int sa_run_create(sa_problem *const *probs, int32_t n_probs, const sa_run_desc *desc,
@@ -393,59 +566,104 @@ extern "C" int sa_run_create(sa_problem *const *probs, int32_t n_probs, const sa
   if (!out) return fail(SA_ERR_ARG, "out is NULL");
   *out = nullptr;
   if (!probs || !desc || !x0_dev) return fail(SA_ERR_ARG, "NULL argument");
-  if (n_probs != 1) return fail(SA_ERR_UNSUPPORTED, "n_probs must be 1 in this version");
-  sa_problem *p = probs[0];
-  if (!p) return fail(SA_ERR_ARG, "problem is NULL");
+  if (n_probs < 1) return fail(SA_ERR_ARG, "n_probs must be >= 1");
+  for (int i = 0; i < n_probs; ++i)
+    if (!probs[i]) return fail(SA_ERR_ARG, "problem %d is NULL", i);
   if (desc->n_chains < 1 || desc->n_chains > (1ll << 31) - 1) return fail(SA_ERR_ARG, "n_chains out of range");
   if (!(desc->T0 > 0) || !(desc->rho > 0)) return fail(SA_ERR_ARG, "T0 and rho must be > 0");
   if (desc->first_stage < 0 || desc->n_stages < 0 || desc->steps_per_stage < 1)
     return fail(SA_ERR_ARG, "stage counts out of range");
-  SA_HIP(hipSetDevice(p->device), "hipSetDevice");
-  const size_t smem = sa::stage_smem_bytes(p->dev, sa::stage_waves_per_block(p->dev));
-  if (smem > 64 * 1024) return fail(SA_ERR_UNSUPPORTED, "stage kernel needs %zu bytes of LDS (> 64 KiB)", smem);
+  if (desc->kernel != SA_KERNEL_AUTO && desc->kernel != SA_KERNEL_PERSISTENT)
+    return fail(SA_ERR_ARG, "unknown kernel %d", desc->kernel);
+  if (desc->chains_per_block != 0 && desc->chains_per_block != 1 && desc->chains_per_block != 2 &&
+      desc->chains_per_block != 4 && desc->chains_per_block != 8)
+    return fail(SA_ERR_ARG, "chains_per_block must be 0 (autotune), 1, 2, 4 or 8");
+  if (desc->record_times && desc->use_graph) return fail(SA_ERR_ARG, "record_times and use_graph exclude each other");
+  const int device = probs[0]->device;
+  for (int i = 1; i < n_probs; ++i)
+    if (probs[i]->device != device) return fail(SA_ERR_ARG, "problems on different devices");
+  SA_HIP(hipSetDevice(device), "hipSetDevice");
+  const bool persistent = n_probs > 1 || desc->kernel == SA_KERNEL_PERSISTENT;
+  if (persistent)
+    for (int i = 0; i < n_probs; ++i)
+      if (probs[i]->dev.nm > sa::kPersistentTilesM)
+        return fail(SA_ERR_UNSUPPORTED, "problem %d: %d nodes exceed the many-network kernel (159)", i,
+                    probs[i]->dev.N);
   const int64_t n = desc->n_chains;
-  const int P = p->info.n_params, E = p->info.n_edges;
   hipStream_t s = (hipStream_t)stream;
 
-  // starting vectors: domain on the host, constraints (hard mode) on the device
-  std::vector<int8_t> hx((size_t)(n * P));
-  SA_HIP(hipMemcpyAsync(hx.data(), x0_dev, hx.size(), hipMemcpyDeviceToHost, s), "copy x0");
-  SA_HIP(hipStreamSynchronize(s), "sync");
-  for (int64_t c = 0; c < n; ++c)
-    for (int i = 0; i < P; ++i) {
-      const int v = hx[(size_t)c * P + i];
-      if (i < E ? (v < -1 || v > 1) : (v < 0 || v > 2))
-        return fail(SA_ERR_DOMAIN, "x0 chain %lld parameter %d = %d", (long long)c, i, v);
-    }
-
   auto *r = new sa_run();
-  r->prob = p;
+  r->probs.assign(probs, probs + n_probs);
   r->desc = *desc;
-  r->device = p->device;
+  r->device = device;
+  r->n = n;
+  r->persistent = persistent;
   r->stream = s;
+  int64_t xo = 0, wo = 0;
+  int32_t max_cost = 0;
+  for (int i = 0; i < n_probs; ++i) {
+    r->x_off.push_back(xo);
+    r->w_off.push_back(wo);
+    xo += n * probs[i]->dev.P;
+    wo += probs[i]->dev.P;
+    max_cost = std::max(max_cost, probs[i]->info.max_cost);
+  }
+  if (!persistent) {
+    const size_t smem = sa::stage_smem_bytes(probs[0]->dev, sa::stage_waves_per_block(probs[0]->dev));
+    if (smem > 64 * 1024) {
+      free_run(r);
+      return fail(SA_ERR_UNSUPPORTED, "stage kernel needs %zu bytes of LDS (> 64 KiB)", smem);
+    }
+  }
+
+  // starting vectors: domain on the host, constraints (hard mode) on the device
+  std::vector<int8_t> hx((size_t)xo);
+  hipError_t e = hipMemcpyAsync(hx.data(), x0_dev, hx.size(), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    free_run(r);
+    return hip_fail(e, "copy x0");
+  }
+  for (int i = 0; i < n_probs; ++i) {
+    const int P = probs[i]->dev.P, E = probs[i]->dev.E;
+    for (int64_t c = 0; c < n; ++c)
+      for (int k = 0; k < P; ++k) {
+        const int v = hx[(size_t)(r->x_off[i] + c * P + k)];
+        if (k < E ? (v < -1 || v > 1) : (v < 0 || v > 2)) {
+          free_run(r);
+          return fail(SA_ERR_DOMAIN, "x0 problem %d chain %lld parameter %d = %d", i, (long long)c, k, v);
+        }
+      }
+  }
+
   const int S = desc->n_stages;
   std::vector<uint32_t> all_tau, tab;
   double T = desc->T0;
   for (int k = 0; k < desc->first_stage; ++k) T = T * desc->rho;
   for (int st = 0; st < S; ++st) {
     int32_t cap;
-    tau_table(T, p->info.max_cost, tab, cap);
+    tau_table(T, max_cost, tab, cap);
     r->tau_off.push_back(all_tau.size());
     r->dcap.push_back(cap);
     all_tau.insert(all_tau.end(), tab.begin(), tab.end());
     T = T * desc->rho;
   }
-  hipError_t e = hipSuccess;
   auto alloc = [&](void **ptr, size_t bytes) {
     if (e == hipSuccess) e = hipMalloc(ptr, bytes ? bytes : 1);
   };
-  alloc((void **)&r->x0, (size_t)(n * P));
-  alloc((void **)&r->xbest, (size_t)(n * P));
-  alloc((void **)&r->xwin, (size_t)P);
-  alloc((void **)&r->cbest, (size_t)n * 4);
-  alloc((void **)&r->cstats, (size_t)n * 16);
+  alloc((void **)&r->x0, (size_t)xo);
+  alloc((void **)&r->xbest, (size_t)xo);
+  alloc((void **)&r->xwin, (size_t)wo);
+  alloc((void **)&r->cbest, (size_t)(n * n_probs) * 4);
+  alloc((void **)&r->cstats, (size_t)(n * n_probs) * 16);
   alloc((void **)&r->tau, all_tau.size() * 4);
-  alloc((void **)&r->rec, (size_t)std::max(S, 1) * sizeof(sa::StageRecord));
+  alloc((void **)&r->queue, 2 * sizeof(uint32_t));
+  alloc((void **)&r->rec, (size_t)std::max(S, 1) * n_probs * sizeof(sa::StageRecord));
+  alloc((void **)&r->probs_dev, (size_t)n_probs * sizeof(sa::DevProblem));
+  alloc((void **)&r->x_off_dev, (size_t)n_probs * 8);
+  alloc((void **)&r->w_off_dev, (size_t)n_probs * 8);
+  alloc((void **)&r->item_net, (size_t)(n * n_probs) * 4);
+  alloc((void **)&r->item_chain0, (size_t)(n * n_probs) * 4);
   for (int st = 0; st < S && desc->record_times && e == hipSuccess; ++st) {
     hipEvent_t a = nullptr, b = nullptr;
     e = hipEventCreate(&a);
@@ -453,30 +671,58 @@ extern "C" int sa_run_create(sa_problem *const *probs, int32_t n_probs, const sa
     r->ev_start.push_back(a);
     r->ev_stop.push_back(b);
   }
-  if (e == hipSuccess) e = hipMemcpyAsync(r->x0, x0_dev, (size_t)(n * P), hipMemcpyDeviceToDevice, s);
+  std::vector<sa::DevProblem> dps;
+  for (sa_problem *p : r->probs) dps.push_back(p->dev);
+  if (e == hipSuccess) e = hipMemcpyAsync(r->x0, x0_dev, (size_t)xo, hipMemcpyDeviceToDevice, s);
   if (e == hipSuccess && !all_tau.empty())
     e = hipMemcpyAsync(r->tau, all_tau.data(), all_tau.size() * 4, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess && p->dev.hard) {
-    // lambda >= 1, so V(x0) = 0 exactly when the cost with lambda equals the
-    // cost with lambda = 0 (the mismatch alone)
-    e = (hipError_t)sa::launch_eval(p->dev, r->x0, n, r->cbest, s);
-    sa::DevProblem m = p->dev;
+  if (e == hipSuccess) e = hipMemcpyAsync(r->probs_dev, dps.data(), dps.size() * sizeof(sa::DevProblem), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(r->x_off_dev, r->x_off.data(), (size_t)n_probs * 8, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(r->w_off_dev, r->w_off.data(), (size_t)n_probs * 8, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemsetAsync(r->queue, 0, 2 * sizeof(uint32_t), s);
+  // lambda >= 1, so V(x0) = 0 exactly when the cost with lambda equals the
+  // cost with lambda = 0 (the mismatch alone)
+  for (int i = 0; i < n_probs && e == hipSuccess; ++i) {
+    const sa::DevProblem &dp = probs[i]->dev;
+    if (!dp.hard) continue;
+    int32_t *c1 = r->cbest, *c0 = (int32_t *)r->cstats;
+    e = (hipError_t)sa::launch_eval(dp, r->x0 + r->x_off[i], n, c1, s);
+    sa::DevProblem m = dp;
     m.lambda = 0;
-    if (e == hipSuccess) e = (hipError_t)sa::launch_eval(m, r->x0, n, (int32_t *)r->cstats, s);
-    std::vector<int32_t> c1((size_t)n), c0((size_t)n);
-    if (e == hipSuccess) e = hipMemcpyAsync(c1.data(), r->cbest, (size_t)n * 4, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(c0.data(), r->cstats, (size_t)n * 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = (hipError_t)sa::launch_eval(m, r->x0 + r->x_off[i], n, c0, s);
+    std::vector<int32_t> h1((size_t)n), h0((size_t)n);
+    if (e == hipSuccess) e = hipMemcpyAsync(h1.data(), c1, (size_t)n * 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h0.data(), c0, (size_t)n * 4, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e == hipSuccess)
       for (int64_t c = 0; c < n; ++c)
-        if (c1[(size_t)c] != c0[(size_t)c]) {
+        if (h1[(size_t)c] != h0[(size_t)c]) {
           free_run(r);
-          return fail(SA_ERR_INFEASIBLE, "x0 of chain %lld breaks a structural constraint", (long long)c);
+          return fail(SA_ERR_INFEASIBLE, "x0 of problem %d chain %lld breaks a structural constraint", i,
+                      (long long)c);
         }
   }
   if (e != hipSuccess) {
     free_run(r);
     return hip_fail(e, "run setup");
+  }
+  if (persistent) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+      r->cus = cus;
+    int rc = SA_OK;
+    if (desc->chains_per_block == 0 && S > 0)
+      rc = autotune_waves(r, s);
+    else
+      rc = upload_items(r, desc->chains_per_block ? desc->chains_per_block : 4);
+    if (rc == SA_OK) {
+      const size_t lds_max = 160 * 1024;
+      if (r->smem > lds_max) rc = fail(SA_ERR_UNSUPPORTED, "many-network kernel needs %zu bytes of LDS", r->smem);
+    }
+    if (rc != SA_OK) {
+      free_run(r);
+      return rc;
+    }
   }
   *out = r;
   return SA_OK;
@@ -488,39 +734,38 @@ extern "C" int sa_run_launch(sa_run *r, int32_t n_stages, void *stream) {
     return fail(SA_ERR_ARG, "stages beyond the schedule (%d launched of %d, asked %d)", r->launched,
                 r->desc.n_stages, n_stages);
   SA_HIP(hipSetDevice(r->device), "hipSetDevice");
-  const sa::DevProblem &pb = r->prob->dev;
-  const int P = pb.P;
-  for (int32_t i = 0; i < n_stages; ++i) {
-    const int32_t st = r->launched;
-    sa::StageArgs a{};
-    a.n_chains = r->desc.n_chains;
-    a.seed = r->desc.seed;
-    a.net = 0;
-    a.stage = r->desc.first_stage + st;
-    a.L = r->desc.steps_per_stage;
-    a.dcap = r->dcap[st];
-    a.tau = r->tau + r->tau_off[st];
-    a.x_start = st == 0 ? r->x0 : r->xwin;
-    a.x_start_stride = st == 0 ? P : 0;
-    a.xbest = r->xbest;
-    a.cbest = r->cbest;
-    a.cstats = r->cstats;
-    const bool timed = !r->ev_start.empty();
-    if (timed) SA_HIP(hipEventRecord(r->ev_start[st], (hipStream_t)stream), "event record");
-    SA_HIP((hipError_t)sa::launch_stage(pb, a, stream), "stage launch");
-    if (timed) SA_HIP(hipEventRecord(r->ev_stop[st], (hipStream_t)stream), "event record");
-    sa::ReduceArgs ra{};
-    ra.n_chains = r->desc.n_chains;
-    ra.P = P;
-    ra.cbest = r->cbest;
-    ra.xbest = r->xbest;
-    ra.cstats = r->cstats;
-    ra.xwin = r->xwin;
-    ra.rec = r->rec + st;
-    SA_HIP((hipError_t)sa::launch_reduce(ra, stream), "reduce launch");
-    r->launched++;
+  hipStream_t s = (hipStream_t)stream;
+  if (n_stages == 0) return SA_OK;
+  if (r->desc.use_graph) {
+    // The stages of this call become one graph (no memset nodes inside),
+    // captured on the run's own stream (the caller's may be the null stream,
+    // which cannot be captured) and launched on the caller's stream.
+    if (!r->capture_stream) SA_HIP(hipStreamCreateWithFlags(&r->capture_stream, hipStreamNonBlocking), "stream create");
+    hipStream_t cs = r->capture_stream;
+    SA_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
+    int rc = SA_OK;
+    for (int32_t i = 0; i < n_stages && rc == SA_OK; ++i) rc = enqueue_stage(r, r->launched + i, cs);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(cs, &g);
+    if (rc != SA_OK) {
+      if (g) hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "end capture");
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+    r->graphs.push_back(x);
+    SA_HIP(hipGraphLaunch(x, s), "graph launch");
+  } else {
+    for (int32_t i = 0; i < n_stages; ++i) {
+      int rc = enqueue_stage(r, r->launched + i, s);
+      if (rc != SA_OK) return rc;
+    }
   }
-  r->stream = (hipStream_t)stream;
+  r->launched += n_stages;
+  r->stream = s;
   return SA_OK;
 }
 
@@ -538,7 +783,7 @@ extern "C" int sa_run_chains(sa_problem *const *probs, int32_t n_probs, const sa
 
 static int sync_run(sa_run *r, int32_t prob) {
   if (!r) return fail(SA_ERR_ARG, "run is NULL");
-  if (prob != 0) return fail(SA_ERR_ARG, "problem index %d out of range", prob);
+  if (prob < 0 || prob >= (int32_t)r->probs.size()) return fail(SA_ERR_ARG, "problem index %d out of range", prob);
   SA_HIP(hipSetDevice(r->device), "hipSetDevice");
   SA_HIP(hipStreamSynchronize(r->stream), "stream sync");
   return SA_OK;
@@ -548,9 +793,13 @@ extern "C" int sa_best(sa_run *r, int32_t prob, int8_t *x_host, int32_t *cost, i
   int rc = sync_run(r, prob);
   if (rc != SA_OK) return rc;
   if (r->launched == 0) return fail(SA_ERR_ARG, "no stage launched");
+  const size_t np = r->probs.size();
   sa::StageRecord rec;
-  SA_HIP(hipMemcpy(&rec, r->rec + (r->launched - 1), sizeof(rec), hipMemcpyDeviceToHost), "copy record");
-  if (x_host) SA_HIP(hipMemcpy(x_host, r->xwin, (size_t)r->prob->dev.P, hipMemcpyDeviceToHost), "copy best");
+  SA_HIP(hipMemcpy(&rec, r->rec + (size_t)(r->launched - 1) * np + prob, sizeof(rec), hipMemcpyDeviceToHost),
+         "copy record");
+  if (x_host)
+    SA_HIP(hipMemcpy(x_host, r->xwin + r->w_off[prob], (size_t)r->probs[prob]->dev.P, hipMemcpyDeviceToHost),
+           "copy best");
   if (cost) *cost = rec.best_cost;
   if (winner) *winner = rec.winner;
   return SA_OK;
@@ -560,17 +809,19 @@ extern "C" int sa_stats(sa_run *r, int32_t prob, sa_stage_stats *out) {
   int rc = sync_run(r, prob);
   if (rc != SA_OK) return rc;
   if (!out) return fail(SA_ERR_ARG, "out is NULL");
-  std::vector<sa::StageRecord> rec((size_t)r->launched);
+  const size_t np = r->probs.size();
+  std::vector<sa::StageRecord> rec((size_t)r->launched * np);
   if (r->launched)
     SA_HIP(hipMemcpy(rec.data(), r->rec, rec.size() * sizeof(sa::StageRecord), hipMemcpyDeviceToHost),
            "copy records");
   for (int32_t i = 0; i < r->launched; ++i) {
-    out[i].best_cost = rec[i].best_cost;
-    out[i].winner = rec[i].winner;
-    out[i].accepted = rec[i].accepted;
-    out[i].uphill = rec[i].uphill;
-    out[i].neutral = rec[i].neutral;
-    out[i].infeasible = rec[i].infeasible;
+    const sa::StageRecord &x = rec[(size_t)i * np + prob];
+    out[i].best_cost = x.best_cost;
+    out[i].winner = x.winner;
+    out[i].accepted = x.accepted;
+    out[i].uphill = x.uphill;
+    out[i].neutral = x.neutral;
+    out[i].infeasible = x.infeasible;
   }
   return SA_OK;
 }
@@ -578,10 +829,21 @@ extern "C" int sa_stats(sa_run *r, int32_t prob, sa_stage_stats *out) {
 extern "C" int sa_chain_best(sa_run *r, int32_t prob, int32_t *cost, int8_t *x_host) {
   int rc = sync_run(r, prob);
   if (rc != SA_OK) return rc;
-  const int64_t n = r->desc.n_chains;
-  if (cost) SA_HIP(hipMemcpy(cost, r->cbest, (size_t)n * 4, hipMemcpyDeviceToHost), "copy chain costs");
+  const int64_t n = r->n;
+  if (cost)
+    SA_HIP(hipMemcpy(cost, r->cbest + (size_t)prob * n, (size_t)n * 4, hipMemcpyDeviceToHost), "copy chain costs");
   if (x_host)
-    SA_HIP(hipMemcpy(x_host, r->xbest, (size_t)(n * r->prob->dev.P), hipMemcpyDeviceToHost), "copy chain bests");
+    SA_HIP(hipMemcpy(x_host, r->xbest + r->x_off[prob], (size_t)(n * r->probs[prob]->dev.P), hipMemcpyDeviceToHost),
+           "copy chain bests");
+  return SA_OK;
+}
+
+extern "C" int sa_run_get_info(sa_run *r, sa_run_info *info) {
+  if (!r || !info) return fail(SA_ERR_ARG, "NULL argument");
+  info->n_probs = (int32_t)r->probs.size();
+  info->kernel = r->persistent ? SA_KERNEL_PERSISTENT : SA_KERNEL_AUTO;
+  info->chains_per_block = r->persistent ? r->waves : sa::stage_waves_per_block(r->probs[0]->dev);
+  info->stages_launched = r->launched;
   return SA_OK;
 }
 

@@ -166,11 +166,16 @@ __device__ __forceinline__ void patch_a(ATile<NM, NK> &A, int reg, uint32_t mask
 }
 
 // Writes parameter p's value v (edge value a, or theta) at its A position.
+// param_pos[p] = lane | m-tile << 8 | k-tile << 12 | dword << 14 | byte << 16,
+// independent of the register layout; the layout's NK turns it into the
+// A register index (mt*NK + kt)*4 + dw.
+template <int NK>
 __device__ __forceinline__ void param_patch_args(const DevProblem &pb, int lane, int p, int v, int &reg,
                                                  uint32_t &mask, uint32_t &bits) {
   const uint32_t pos = pb.param_pos[p];
   const int a = p < pb.E ? v : -v;  // -theta in the bias column
-  reg = (int)((pos >> 8) & 0xffu);
+  const int mt = (int)((pos >> 8) & 15u), kt = (int)((pos >> 12) & 3u), dw = (int)((pos >> 14) & 3u);
+  reg = (mt * NK + kt) * 4 + dw;
   mask = (lane == (int)(pos & 63u)) ? (0xffu << (8 * ((pos >> 16) & 3u))) : 0u;
   bits = ((uint32_t)a & 0xffu) * kLowBits;
 }
@@ -186,7 +191,7 @@ __device__ __forceinline__ void build_a(ATile<NM, NK> &A, const DevProblem &pb, 
     const int v = uniform(xv(p));
     int reg;
     uint32_t mask, bits;
-    param_patch_args(pb, lane, p, v, reg, mask, bits);
+    param_patch_args<NK>(pb, lane, p, v, reg, mask, bits);
     patch_a(A, uniform(reg), mask, bits);
   }
 }
@@ -255,22 +260,23 @@ __device__ __forceinline__ void write_states(const v4i (&B)[NK], const DevProble
     }
 }
 
-// Simulates every condition for the chain whose parameters are in A and
-// returns this lane's share of the mismatch M (§2.3).  Synchronous update of
-// §2.2: every m-tile of step t reads only the states of step t-1 (B) and
-// writes the states of step t (NB).  obs_r/obs_w: [CG][K][nd][64] tables.
 // One synchronous time step (§2.2): every m-tile reads only the states of
 // step t-1 (B) and writes those of step t (NB).  Clamped bytes (mask CM) get
-// their old state as target, so they hold.
-template <int NM, int NK, int D>
+// their old state as target, so they hold.  With RT only the first nm
+// m-tiles and nk k-tiles are present (a smaller network in a larger layout).
+template <int NM, int NK, int D, bool RT>
 __device__ __forceinline__ void time_step(const ATile<NM, NK> &A, const v4i (&B)[NK], v4i (&NB)[NK],
-                                          const v4i (&CM)[NK]) {
+                                          const v4i (&CM)[NK], int nm, int nk) {
   static_for<NM>([&](auto mtc) SA_INLINE {
     constexpr int mt = decltype(mtc)::value;
+    if (RT && mt >= nm) {
+      NB[mt >> 2][mt & 3] = B[mt >> 2][mt & 3];
+      return;
+    }
     v4i acc = {0, 0, 0, 0};
     static_for<NK>([&](auto ktc) SA_INLINE {
       constexpr int kt = decltype(ktc)::value;
-      acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(afrag<mt, kt>(A), B[kt], acc, 0, 0, 0);
+      if (!RT || kt < nk) acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(afrag<mt, kt>(A), B[kt], acc, 0, 0, 0);
     });
     const uint32_t s = (uint32_t)B[mt >> 2][mt & 3];
     const uint32_t cm = (uint32_t)CM[mt >> 2][mt & 3];
@@ -288,21 +294,23 @@ __device__ __forceinline__ void time_step(const ATile<NM, NK> &A, const v4i (&B)
 // Simulates every condition for the chain whose parameters are in A and
 // returns this lane's share of the mismatch M (§2.3).  obs_r/obs_w:
 // [CG][K][nd][64] tables.  The two state buffers alternate between steps.
-template <int NM, int NK, int D, bool TRAJ>
+template <int NM, int NK, int D, bool TRAJ, bool RT = false>
 __device__ __forceinline__ int lane_mismatch(const ATile<NM, NK> &A, const DevProblem &pb, int lane,
                                              const uint32_t *obs_r, const uint32_t *obs_w,
                                              int8_t *__restrict__ traj) {
+  const int nm = RT ? pb.nm : NM, nk = RT ? pb.nk : NK;
   int total = 0;
   for (int cg = 0; cg < pb.CG; ++cg) {
     v4i B0[NK], B1[NK], CM[NK];
-    const int base = cg * 4 * NK;
+    const int base = cg * 4 * nk;
 #pragma unroll
     for (int kt = 0; kt < NK; ++kt)
 #pragma unroll
       for (int dw = 0; dw < 4; ++dw) {
+        const bool present = !RT || kt < nk;
         const int at = (base + kt * 4 + dw) * kWave + lane;
-        B0[kt][dw] = (int)pb.b0[at];
-        CM[kt][dw] = (int)pb.cmask[at];
+        B0[kt][dw] = present ? (int)pb.b0[at] : 0;
+        CM[kt][dw] = present ? (int)pb.cmask[at] : -1;
       }
     const int c = cg * 16 + (lane & 15);
     const uint32_t *rbase = obs_r + (size_t)cg * pb.K * pb.nd * kWave;
@@ -320,13 +328,13 @@ __device__ __forceinline__ int lane_mismatch(const ATile<NM, NK> &A, const DevPr
     observe(B0, 0);
     int t = 1;
     for (; t + 1 <= pb.T; t += 2) {
-      time_step<NM, NK, D>(A, B0, B1, CM);
+      time_step<NM, NK, D, RT>(A, B0, B1, CM, nm, nk);
       observe(B1, t);
-      time_step<NM, NK, D>(A, B1, B0, CM);
+      time_step<NM, NK, D, RT>(A, B1, B0, CM, nm, nk);
       observe(B0, t + 1);
     }
     if (t <= pb.T) {
-      time_step<NM, NK, D>(A, B0, B1, CM);
+      time_step<NM, NK, D, RT>(A, B0, B1, CM, nm, nk);
       observe(B1, t);
     }
   }

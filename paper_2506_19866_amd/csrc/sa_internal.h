@@ -37,7 +37,8 @@ struct DevProblem {
   int32_t d;       // step size
   int32_t hard;
   int32_t lambda;
-  // [P]: lane | (register << 8) | (byte << 16) of the A entry of parameter p
+  // [P]: lane | m-tile << 8 | k-tile << 12 | dword << 14 | byte << 16 of the
+  // A entry of parameter p (independent of the register layout)
   const uint32_t *param_pos;
   const int32_t *edge_src, *edge_dst;  // [E]
   const int32_t *in_ptr;               // [N+1]
@@ -74,22 +75,59 @@ struct StageRecord {
   uint64_t accepted, uphill, neutral, infeasible;
 };
 
-struct ReduceArgs {
+
+// One temperature stage of many networks in one persistent launch (per step
+// size d present): blocks take work items (a network and `waves` of its
+// chains) from a queue in longest-first order until it is empty.
+struct BatchArgs {
+  const DevProblem *probs;    // [n_probs], device copy
+  int32_t n_probs;
+  int64_t n_chains;           // per network
+  const int32_t *item_net;    // [n_items]
+  const int32_t *item_chain0; // [n_items]
+  int32_t n_items;
+  int32_t waves;              // chains per work item = waves per block
+  uint32_t *queue;            // next item; zero when the launch starts
+  uint64_t seed;
+  int32_t stage, L, dcap;
+  const uint32_t *tau;        // [dcap+1]
+  const int8_t *x_start;      // first stage: x0 at x_off; later: winners at w_off
+  int32_t first;
+  const int64_t *x_off;       // [n_probs]: byte offset of the network's chain vectors
+  const int64_t *w_off;       // [n_probs]: byte offset of the network's winner vector
+  int8_t *xbest;              // at x_off
+  int32_t *cbest;             // [n_probs * n_chains]
+  uint32_t *cstats;           // [n_probs * n_chains * 4]
+};
+
+// Table 1's serial part for every network of a run (one block per network):
+// winner, its vector copied for the next stage, statistics summed; also resets
+// the work queue of the persistent kernel.
+struct BatchReduceArgs {
+  int32_t n_probs;
   int64_t n_chains;
-  int32_t P;
+  const DevProblem *probs;
+  const int64_t *x_off, *w_off;
   const int32_t *cbest;
   const int8_t *xbest;
   const uint32_t *cstats;
-  int8_t *xwin;           // [P] out
-  StageRecord *rec;       // this stage's record (out)
+  int8_t *xwin;
+  StageRecord *rec;           // [n_probs] of this stage
+  uint32_t *queue;            // [2] work counters to reset, or null
 };
 
-// Launch wrappers (sa_k_batch.hip, sa_k_stage.hip).  All return a hipError_t as int.
+// Launch wrappers (sa_k_batch.hip, sa_k_stage.hip, sa_k_persist.hip).  All
+// return a hipError_t as int.
 int launch_eval(const DevProblem &pb, const int8_t *x, int64_t n, int32_t *cost, void *stream);
 int launch_simulate(const DevProblem &pb, const int8_t *x, int64_t n, int8_t *traj, void *stream);
 int launch_stage(const DevProblem &pb, const StageArgs &sa, void *stream);
-int launch_reduce(const ReduceArgs &ra, void *stream);
 size_t stage_smem_bytes(const DevProblem &pb, int waves_per_block);
 int stage_waves_per_block(const DevProblem &pb);
+int launch_persistent(const BatchArgs &a, int d, int grid, size_t smem, void *stream);
+int launch_batch_reduce(const BatchReduceArgs &ra, void *stream);
+size_t persistent_smem_bytes(const DevProblem &pb, int waves);
+// Workgroups of `waves` waves with `smem` bytes of LDS that fit on one CU.
+int persistent_blocks_per_cu(int waves, size_t smem);
+constexpr int kPersistentTilesM = 10, kPersistentTilesK = 3;  // networks up to 159 nodes
 
 }  // namespace sa

@@ -1,5 +1,5 @@
-// sa_k_batch.hip -- kernels over batches of vectors (cost, trajectories)
-// and the per-stage reduction of Table 1.
+// sa_k_batch.hip -- kernels over batches of vectors: cost (§2.3, §2.5.3) and
+// trajectories (§2.2) of n parameter vectors, one wave per vector.
 #include "sa_device.h"
 
 namespace sa {
@@ -33,53 +33,6 @@ __global__ __launch_bounds__(256) void simulate_kernel(DevProblem pb, const int8
   SA_DECLARE_A(A, NM, NK);
   build_a(A, pb, lane, xv);
   lane_mismatch<NM, NK, D, true>(A, pb, lane, pb.obs_r, pb.obs_w, traj + (size_t)i * pb.C * (pb.T + 1) * pb.N);
-}
-
-// ---------------------------------------------------------------------------
-// K2: Table 1's serial part on the device: global best over the chains
-// (lowest chain id on ties), its vector copied for the next stage, and the
-// stage's statistics summed.  One block of 256.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs ra) {
-  __shared__ unsigned long long keys[256];
-  __shared__ unsigned long long sums[4][256];
-  const int tid = threadIdx.x;
-  unsigned long long best = ~0ull;
-  unsigned long long s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-  for (int64_t c = tid; c < ra.n_chains; c += 256) {
-    const unsigned long long key = ((unsigned long long)(uint32_t)ra.cbest[c] << 32) | (unsigned long long)c;
-    best = key < best ? key : best;
-    s0 += ra.cstats[c * 4 + 0];
-    s1 += ra.cstats[c * 4 + 1];
-    s2 += ra.cstats[c * 4 + 2];
-    s3 += ra.cstats[c * 4 + 3];
-  }
-  keys[tid] = best;
-  sums[0][tid] = s0;
-  sums[1][tid] = s1;
-  sums[2][tid] = s2;
-  sums[3][tid] = s3;
-  __syncthreads();
-  for (int half = 128; half > 0; half >>= 1) {
-    if (tid < half) {
-      const unsigned long long o = keys[tid + half];
-      keys[tid] = o < keys[tid] ? o : keys[tid];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) sums[q][tid] += sums[q][tid + half];
-    }
-    __syncthreads();
-  }
-  const int64_t winner = (int64_t)(keys[0] & 0xffffffffull);
-  if (tid == 0) {
-    ra.rec->best_cost = (int32_t)(keys[0] >> 32);
-    ra.rec->winner = (int32_t)winner;
-    ra.rec->accepted = sums[0][0];
-    ra.rec->uphill = sums[1][0];
-    ra.rec->neutral = sums[2][0];
-    ra.rec->infeasible = sums[3][0];
-  }
-  const int8_t *from = ra.xbest + winner * ra.P;
-  for (int i = tid; i < ra.P; i += 256) ra.xwin[i] = from[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -123,9 +76,5 @@ int launch_simulate(const DevProblem &pb, const int8_t *x, int64_t n, int8_t *tr
   return (int)hipGetLastError();
 }
 
-int launch_reduce(const ReduceArgs &ra, void *stream) {
-  reduce_kernel<<<1, 256, 0, (hipStream_t)stream>>>(ra);
-  return (int)hipGetLastError();
-}
 
 }  // namespace sa

@@ -1,0 +1,130 @@
+// sa_k_persist.hip -- many networks of uneven size in one persistent launch
+// per temperature stage (Table 1 for every network), and the per-network
+// stage reduction.  Every network runs in the largest register layout with
+// its own tile counts as runtime bounds, so one kernel serves all sizes.
+#include "sa_chain.h"
+
+namespace sa {
+
+constexpr int kNMx = kPersistentTilesM, kNKx = kPersistentTilesK;
+
+template <int D>
+__global__ __launch_bounds__(512) void persistent_kernel(BatchArgs a) {
+  extern __shared__ uint32_t smem[];
+  __shared__ int s_item;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = threadIdx.x >> 6;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = (int)atomicAdd(a.queue, 1u);
+    __syncthreads();
+    const int item = s_item;
+    __syncthreads();  // every wave has read the item before the next fetch
+    if (item >= a.n_items) break;
+    const int net = a.item_net[item];
+    const DevProblem pb = a.probs[net];  // every item of this launch has step size D
+    const int n_obs = obs_dwords(pb);
+    uint32_t *lds_r = smem, *lds_w = smem + n_obs;
+    for (int i = threadIdx.x; i < n_obs; i += blockDim.x) {
+      lds_r[i] = pb.obs_r[i];
+      lds_w[i] = pb.obs_w[i];
+    }
+    __syncthreads();
+    const int64_t chain = (int64_t)a.item_chain0[item] + wv;
+    if (wv < a.waves && chain < a.n_chains) {
+      const int64_t gc = (int64_t)net * a.n_chains + chain;
+      ChainJob job;
+      job.x_start = a.first ? a.x_start + a.x_off[net] + chain * pb.P : a.x_start + a.w_off[net];
+      job.xbest = a.xbest + a.x_off[net] + chain * pb.P;
+      job.cbest = a.cbest + gc;
+      job.stats = a.cstats + gc * 4;
+      job.seed = a.seed;
+      job.chain = (uint64_t)chain;
+      job.net = (uint64_t)net;
+      job.g0 = (uint64_t)a.stage * (uint64_t)a.L;
+      job.L = a.L;
+      job.dcap = a.dcap;
+      job.tau = a.tau;
+      uint8_t *lds = reinterpret_cast<uint8_t *>(smem + 2 * n_obs) + (size_t)wv * chain_lds_bytes(pb);
+      run_chain<kNMx, kNKx, D, true>(pb, job, lane, lds, lds_r, lds_w);
+    }
+    __syncthreads();  // the block's LDS is reused by the next item
+  }
+}
+
+__global__ __launch_bounds__(256) void batch_reduce_kernel(BatchReduceArgs ra) {
+  __shared__ unsigned long long keys[256];
+  __shared__ unsigned long long sums[4][256];
+  const int tid = threadIdx.x;
+  const int net = blockIdx.x;
+  const int64_t base = (int64_t)net * ra.n_chains;
+  unsigned long long best = ~0ull;
+  unsigned long long s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  for (int64_t c = tid; c < ra.n_chains; c += 256) {
+    const unsigned long long key = ((unsigned long long)(uint32_t)ra.cbest[base + c] << 32) | (unsigned long long)c;
+    best = key < best ? key : best;
+    const uint32_t *st = ra.cstats + (base + c) * 4;
+    s0 += st[0];
+    s1 += st[1];
+    s2 += st[2];
+    s3 += st[3];
+  }
+  keys[tid] = best;
+  sums[0][tid] = s0;
+  sums[1][tid] = s1;
+  sums[2][tid] = s2;
+  sums[3][tid] = s3;
+  __syncthreads();
+  for (int half = 128; half > 0; half >>= 1) {
+    if (tid < half) {
+      const unsigned long long o = keys[tid + half];
+      keys[tid] = o < keys[tid] ? o : keys[tid];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sums[q][tid] += sums[q][tid + half];
+    }
+    __syncthreads();
+  }
+  const int64_t winner = (int64_t)(keys[0] & 0xffffffffull);
+  if (tid == 0) {
+    StageRecord *r = ra.rec + net;
+    r->best_cost = (int32_t)(keys[0] >> 32);
+    r->winner = (int32_t)winner;
+    r->accepted = sums[0][0];
+    r->uphill = sums[1][0];
+    r->neutral = sums[2][0];
+    r->infeasible = sums[3][0];
+    if (net == 0 && ra.queue) {  // one queue per step-size class
+      ra.queue[0] = 0u;
+      ra.queue[1] = 0u;
+    }
+  }
+  const int P = ra.probs[net].P;
+  const int8_t *from = ra.xbest + ra.x_off[net] + winner * P;
+  int8_t *to = ra.xwin + ra.w_off[net];
+  for (int i = tid; i < P; i += 256) to[i] = from[i];
+}
+
+size_t persistent_smem_bytes(const DevProblem &pb, int waves) {
+  return (size_t)2 * obs_dwords(pb) * 4 + (size_t)waves * chain_lds_bytes(pb);
+}
+
+int persistent_blocks_per_cu(int waves, size_t smem) {
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, persistent_kernel<1>, 64 * waves, smem) != hipSuccess)
+    return 1;
+  return blocks > 0 ? blocks : 1;
+}
+
+int launch_persistent(const BatchArgs &a, int d, int grid, size_t smem, void *stream) {
+  if (d == 1)
+    persistent_kernel<1><<<grid, 64 * a.waves, smem, (hipStream_t)stream>>>(a);
+  else
+    persistent_kernel<2><<<grid, 64 * a.waves, smem, (hipStream_t)stream>>>(a);
+  return (int)hipGetLastError();
+}
+
+int launch_batch_reduce(const BatchReduceArgs &ra, void *stream) {
+  batch_reduce_kernel<<<ra.n_probs, 256, 0, (hipStream_t)stream>>>(ra);
+  return (int)hipGetLastError();
+}
+
+}  // namespace sa

@@ -18,10 +18,11 @@ SA_OK = 0
 SA_ERR_ARG, SA_ERR_DOMAIN, SA_ERR_TOPOLOGY, SA_ERR_INFEASIBLE = -1, -2, -3, -4
 SA_ERR_DEVICE, SA_ERR_OOM, SA_ERR_UNSUPPORTED, SA_ERR_OVERFLOW = -5, -6, -7, -8
 SA_HARD, SA_PENALTY = 0, 1
+SA_KERNEL_AUTO, SA_KERNEL_PERSISTENT = 0, 1
 
 EXPORTS = ("sa_create_problem", "sa_destroy_problem", "sa_problem_get_info", "sa_eval_cost",
            "sa_simulate", "sa_run_create", "sa_run_launch", "sa_run_chains", "sa_best", "sa_stats",
-           "sa_chain_best", "sa_stage_times", "sa_destroy_run", "sa_last_error")
+           "sa_chain_best", "sa_stage_times", "sa_run_get_info", "sa_destroy_run", "sa_last_error")
 
 
 class SAError(RuntimeError):
@@ -53,8 +54,14 @@ class _RunDesc(C.Structure):
     _fields_ = [
         ("n_chains", C.c_int64), ("seed", C.c_uint64), ("T0", C.c_double), ("rho", C.c_double),
         ("first_stage", C.c_int32), ("n_stages", C.c_int32), ("steps_per_stage", C.c_int32),
-        ("record_times", C.c_int32),
+        ("record_times", C.c_int32), ("kernel", C.c_int32), ("chains_per_block", C.c_int32),
+        ("use_graph", C.c_int32),
     ]
+
+
+class _RunInfo(C.Structure):
+    _fields_ = [("n_probs", C.c_int32), ("kernel", C.c_int32), ("chains_per_block", C.c_int32),
+                ("stages_launched", C.c_int32)]
 
 
 class _StageStats(C.Structure):
@@ -88,6 +95,7 @@ def lib():
         L.sa_stats.argtypes = [vp, C.c_int32, vp]
         L.sa_chain_best.argtypes = [vp, C.c_int32, vp, vp]
         L.sa_stage_times.argtypes = [vp, C.c_int32, vp]
+        L.sa_run_get_info.argtypes = [vp, C.POINTER(_RunInfo)]
         L.sa_destroy_run.argtypes = [vp]
         L.sa_last_error.restype = C.c_char_p
         for name in EXPORTS:
@@ -196,25 +204,36 @@ class Problem:
 
 
 class Run:
-    """Parallel annealing of one problem (Table 1).  create=True only sets the
+    """Parallel annealing (Table 1) of one problem or of several independent
+    problems in one persistent launch per stage.  launch=False only sets the
     run up; launch(k) queues the next k stages."""
 
-    def __init__(self, problem: Problem, x0, *, seed: int, T0: float, rho: float, n_stages: int,
+    def __init__(self, problems, x0, *, seed: int, T0: float, rho: float, n_stages: int,
                  steps_per_stage: int, first_stage: int = 0, stream=None, launch: bool = True,
-                 record_times: bool = False):
+                 record_times: bool = False, kernel: int = SA_KERNEL_AUTO, chains_per_block: int = 0,
+                 use_graph: bool = False):
+        """problems: a Problem or a list of them; x0: int8 CUDA tensor [n_chains, P]
+        for one problem, or a list (one [n_chains, P_p] tensor per problem)."""
         import torch
-        x0 = _device_tensor(x0, torch.int8, problem.n_params)
-        self.problem = problem
-        self.n_chains = x0.shape[0]
+        if isinstance(problems, Problem):
+            problems, x0 = [problems], [x0]
+        self.problems = list(problems)
+        xs = [_device_tensor(x, torch.int8, p.n_params) for p, x in zip(self.problems, x0)]
+        n = xs[0].shape[0]
+        if any(x.shape[0] != n for x in xs):
+            raise ValueError("every problem needs the same number of chains")
+        self._x0 = torch.cat([x.reshape(-1) for x in xs]) if len(xs) > 1 else xs[0]
+        self.problem = self.problems[0]
+        self.n_chains = n
         self.n_stages = n_stages
         self.launched = 0
-        d = _RunDesc(self.n_chains, int(seed) & (2**64 - 1), float(T0), float(rho), int(first_stage),
-                     int(n_stages), int(steps_per_stage), 1 if record_times else 0)
-        self._x0 = x0
-        probs = (C.c_void_p * 1)(problem.handle)
+        d = _RunDesc(n, int(seed) & (2**64 - 1), float(T0), float(rho), int(first_stage), int(n_stages),
+                     int(steps_per_stage), 1 if record_times else 0, int(kernel), int(chains_per_block),
+                     1 if use_graph else 0)
+        probs = (C.c_void_p * len(self.problems))(*[p.handle for p in self.problems])
         h = C.c_void_p()
-        _check(lib().sa_run_create(probs, 1, C.byref(d), C.c_void_p(x0.data_ptr()), C.byref(h),
-                                   _stream_handle(stream)))
+        _check(lib().sa_run_create(probs, len(self.problems), C.byref(d), C.c_void_p(self._x0.data_ptr()),
+                                   C.byref(h), _stream_handle(stream)))
         self._h = h
         if launch:
             self.launch(n_stages, stream=stream)
@@ -223,24 +242,28 @@ class Run:
         _check(lib().sa_run_launch(self._h, int(n_stages), _stream_handle(stream)))
         self.launched += n_stages
 
-    def best(self):
-        x = np.zeros(self.problem.n_params, dtype=np.int8)
+    def info(self) -> dict:
+        i = _RunInfo()
+        _check(lib().sa_run_get_info(self._h, C.byref(i)))
+        return {k: getattr(i, k) for k, _ in _RunInfo._fields_}
+
+    def best(self, prob: int = 0):
+        x = np.zeros(self.problems[prob].n_params, dtype=np.int8)
         cost, winner = C.c_int32(), C.c_int32()
-        _check(lib().sa_best(self._h, 0, x.ctypes.data, C.byref(cost), C.byref(winner)))
+        _check(lib().sa_best(self._h, prob, x.ctypes.data, C.byref(cost), C.byref(winner)))
         return x, cost.value, winner.value
 
-    def stats(self) -> dict:
+    def stats(self, prob: int = 0) -> dict:
         arr = (_StageStats * max(self.launched, 1))()
-        _check(lib().sa_stats(self._h, 0, C.cast(arr, C.c_void_p)))
-        out = {k: np.array([getattr(arr[i], k) for i in range(self.launched)],
-                           dtype=np.int64 if k in ("best_cost", "winner") else np.uint64)
-               for k, _ in _StageStats._fields_}
-        return out
+        _check(lib().sa_stats(self._h, prob, C.cast(arr, C.c_void_p)))
+        return {k: np.array([getattr(arr[i], k) for i in range(self.launched)],
+                            dtype=np.int64 if k in ("best_cost", "winner") else np.uint64)
+                for k, _ in _StageStats._fields_}
 
-    def chain_best(self):
+    def chain_best(self, prob: int = 0):
         cost = np.zeros(self.n_chains, dtype=np.int32)
-        x = np.zeros((self.n_chains, self.problem.n_params), dtype=np.int8)
-        _check(lib().sa_chain_best(self._h, 0, cost.ctypes.data, x.ctypes.data))
+        x = np.zeros((self.n_chains, self.problems[prob].n_params), dtype=np.int8)
+        _check(lib().sa_chain_best(self._h, prob, cost.ctypes.data, x.ctypes.data))
         return cost, x
 
     def stage_times_ms(self) -> np.ndarray:

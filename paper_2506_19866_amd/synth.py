@@ -203,6 +203,60 @@ CONFIGS = {
 }
 
 
+# Batched uneven workload: 256 independent networks of 10-150 nodes, each with
+# its own conditions and data, 256 chains per network in one persistent launch.
+BATCH = dict(name="c4", n_networks=256, nodes=(10, 150), mean_indegree=(2.0, 5.0), conditions=(4, 16),
+             steps=(10, 20), times=(3, 5), clamps=(1, 2), noise=0.05,
+             chains=256, stages=100, steps_per_stage=200, T0=2.0, T_end=0.01)
+
+
+def batch_network_config(i: int) -> dict:
+    """Sizes of network i of the batched workload (seed 4000 + i)."""
+    rng = rng_for(4000 + i)
+    N = int(rng.integers(BATCH["nodes"][0], BATCH["nodes"][1] + 1))
+    k = float(rng.uniform(*BATCH["mean_indegree"]))
+    C = int(rng.integers(BATCH["conditions"][0], BATCH["conditions"][1] + 1))
+    T = int(rng.integers(BATCH["steps"][0], BATCH["steps"][1] + 1))
+    K = int(rng.integers(BATCH["times"][0], BATCH["times"][1] + 1))
+    return dict(n_nodes=N, n_edges=int(round(k * N)), topology="cycle_plus_uniform", n_cond=C,
+                clamps=BATCH["clamps"], n_steps=T, n_times=K, n_obs=-(-N // 3), noise=BATCH["noise"],
+                seed=4000 + i, min_nonzero=0.15)
+
+
+def load_batch(name: str = "c4") -> list:
+    """The stored batched workload as a list of problem dicts."""
+    path = os.path.join(DATA_DIR, f"{name}.npz")
+    with np.load(path, allow_pickle=False) as z:
+        files = {k: z[k] for k in z.files}
+    n = int(files["n_networks"])
+    out = []
+    for i in range(n):
+        pre = f"n{i}_"
+        prob = {k[len(pre):]: v for k, v in files.items() if k.startswith(pre)}
+        for k in _INT_KEYS:
+            prob[k] = int(prob[k])
+        out.append(prob)
+    return out
+
+
+def save_batch(path: str, probs: list) -> None:
+    arrays = {"n_networks": np.int64(len(probs))}
+    for i, prob in enumerate(probs):
+        for k, v in prob.items():
+            arrays[f"n{i}_{k}"] = np.int64(v) if k in _INT_KEYS else np.asarray(v)
+    np.savez_compressed(path, **arrays)
+
+
+def batch_start_vectors(probs: list, n_chains: int) -> list:
+    """Per-network starting vectors of the batched workload (feasible)."""
+    return [feasible_params(rng_for(6000 + i), n_chains, p["row_ptr"], p["src"]) for i, p in enumerate(probs)]
+
+
+def batch_schedule() -> dict:
+    return dict(n_chains=BATCH["chains"], n_stages=BATCH["stages"], steps_per_stage=BATCH["steps_per_stage"],
+                T0=BATCH["T0"], rho=cooling_factor(BATCH["T0"], BATCH["T_end"], BATCH["stages"]), seed=2004)
+
+
 def problem_seed(name: str) -> int:
     return 1000 + int(name[1:])
 
