@@ -451,3 +451,47 @@ def test_annealing_reaches_global_minimum_on_tiny_networks():
         r = o.run(x0, seed=seed, T0=2.0, rho=0.9, n_stages=30, steps_per_stage=100)
         hits += r["cost"] == best
     assert hits >= 4
+
+
+# ---------------------------------------------------------------------------
+# the float64 reference of the proposal network
+# ---------------------------------------------------------------------------
+def test_mlp_reference_gradients_match_finite_differences():
+    from oracle import mlp_reference as M
+    rng = np.random.default_rng(0)
+    n = 9
+    X = rng.normal(size=(n, M.IN))
+    y = (rng.random(n) < 0.4).astype(float)
+    p = {"W1": rng.normal(size=(M.IN, M.HIDDEN)) * 0.2, "b1": rng.normal(size=M.HIDDEN) * 0.1,
+         "W2": rng.normal(size=M.HIDDEN) * 0.2, "b2": 0.3}
+    g = M.grads(X, y, **p)
+    h = 1e-6
+    for key, idx in (("W1", (3, 17)), ("W1", (0, 200)), ("b1", (5,)), ("W2", (255,)), ("W2", (8,)), ("b2", None)):
+        plus = {k: np.array(v, dtype=float, copy=True) for k, v in p.items()}
+        minus = {k: np.array(v, dtype=float, copy=True) for k, v in p.items()}
+        if idx is None:
+            plus[key] = p[key] + h
+            minus[key] = p[key] - h
+            analytic = g[key]
+        else:
+            plus[key][idx] += h
+            minus[key][idx] -= h
+            analytic = g[key][idx]
+        numeric = (M.loss(X, y, **plus) - M.loss(X, y, **minus)) / (2 * h)
+        assert abs(numeric - analytic) < 1e-6 + 1e-5 * abs(numeric), (key, idx, numeric, analytic)
+
+
+def test_mlp_reference_adam_reduces_loss_and_bf16_rounding():
+    from oracle import mlp_reference as M
+    assert M.bf16(np.array([1.0, 1.00390625, 1.005859375]))[1] == 1.0          # tie to even
+    assert M.bf16(np.array([1.005859375]))[0] == 1.0078125
+    rng = np.random.default_rng(1)
+    X = rng.normal(size=(256, M.IN))
+    y = (X[:, 0] - X[:, 1] > 0).astype(float)
+    p = {"W1": rng.normal(size=(M.IN, M.HIDDEN)) * 0.1, "b1": np.zeros(M.HIDDEN),
+         "W2": rng.normal(size=M.HIDDEN) * 0.1, "b2": 0.0}
+    state = {}
+    first = M.loss(X, y, **p)
+    for _ in range(60):
+        M.adam(p, M.grads(X, y, **p), state, lr=1e-2)
+    assert M.loss(X, y, **p) < 0.5 * first
