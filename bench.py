@@ -145,6 +145,93 @@ def bench_batch(args) -> int:
     return 0
 
 
+def _curve(run, sched_L, n):
+    """(cumulative stage-kernel seconds, global best after each stage)."""
+    st = run.stats()
+    ms = run.stage_times_ms().astype(np.float64)
+    return np.cumsum(ms) * 1e-3, np.minimum.accumulate(st["best_cost"].astype(np.int64))
+
+
+def _time_to(curve, target):
+    t, best = curve
+    hit = np.flatnonzero(best <= target)
+    return float(t[hit[0]]) if hit.size else None
+
+
+def bench_learned(args) -> int:
+    """The learned proposal against the plain one on the Mtb-scale workload:
+    traces of plain runs on the HPG-scale workload (about args.trace_rows
+    rows), the network trained on them, then plain and learned runs of the
+    full c3 schedule for several seeds, compared by the stage-kernel time
+    they need to reach (a) the median final cost of the plain runs and (b)
+    the cost of the generating parameters on the noisy data."""
+    import torch
+    from paper_2506_19866_amd import proposal, sa, synth
+    p2, s2 = synth.load_workload("c2"), synth.bench_schedule("c2")
+    P2 = sa.Problem(p2)
+    n2, L2 = s2["n_chains"], s2["steps_per_stage"]
+    x2 = torch.from_numpy(synth.start_vectors("c2", p2, n2)).cuda()
+    te = max(1, (n2 * s2["n_stages"] * L2) // args.trace_rows)
+    t0 = time.perf_counter()
+    X, y, _ = proposal.collect(P2, x2, seed=s2["seed"], T0=s2["T0"], rho=s2["rho"], n_stages=s2["n_stages"],
+                               steps_per_stage=L2, trace_every=te, refresh_every=args.refresh)
+    torch.cuda.synchronize()
+    t_collect = time.perf_counter() - t0
+    pos = float(y.mean().item())
+    log(f"[learned] traces: {X.shape[0]} rows from c2 (every {te}th step), {pos:.4f} improving, {t_collect:.2f} s")
+    net = sa.Mlp(proposal.init_params(args.model_seed))
+    t0 = time.perf_counter()
+    losses = proposal.train(net, X, y, epochs=args.epochs, batch=8192, lr=args.lr, seed=args.model_seed, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del X, y
+
+    p3, s3 = synth.load_workload("c3"), synth.bench_schedule("c3")
+    P3 = sa.Problem(p3)
+    n3, L3, S3 = s3["n_chains"], s3["steps_per_stage"], s3["n_stages"]
+    x3 = torch.from_numpy(synth.start_vectors("c3", p3, n3)).cuda()
+    hidden_cost = int(P3.eval_cost(torch.from_numpy(p3["hidden"][None, :]).cuda()).item())
+    curves = {"plain": [], "learned": []}
+    for k in range(args.eval_seeds):
+        seed = s3["seed"] + 100 * k
+        for kind in ("plain", "learned"):
+            extra = dict(model=net, refresh_every=args.refresh, eps_plain=args.eps) if kind == "learned" else {}
+            run = sa.Run(P3, x3, seed=seed, T0=s3["T0"], rho=s3["rho"], n_stages=S3, steps_per_stage=L3,
+                         record_times=True, **extra)
+            curves[kind].append(_curve(run, L3, n3))
+            run.close()
+            log(f"[learned] seed {seed} {kind}: final best {int(curves[kind][-1][1][-1])} "
+                f"in {curves[kind][-1][0][-1]:.2f} s of stage kernels")
+    finals = {k: [int(c[1][-1]) for c in v] for k, v in curves.items()}
+    target = int(np.median(finals["plain"]))
+    tt = {k: [_time_to(c, target) for c in v] for k, v in curves.items()}
+    th = {k: [_time_to(c, hidden_cost) for c in v] for k, v in curves.items()}
+    total = {k: [float(c[0][-1]) for c in v] for k, v in curves.items()}
+
+    def med(vals):
+        vals = [v for v in vals if v is not None]
+        return float(np.median(vals)) if vals else None
+    value = med(tt["learned"])
+    out = {
+        "metric": "c3 time to the plain runs' median final cost, learned proposal", "value": value, "unit": "s",
+        "n_gpus": 1, "steps": S3, "warmup": 0, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int8 simulation, bf16 network",
+        "data": "synthetic (traces from c2 plain runs; evaluation on the stored c3 workload)",
+        "config": {"workload": f"c3 ({n3} chains x {L3} steps x {S3} stages), network trained on {te}-strided "
+                               f"traces of c2 plain runs", "refresh_every": args.refresh, "eps_plain": args.eps,
+                   "eval_seeds": args.eval_seeds, "epochs": args.epochs},
+        "plain_time_to_target_s": tt["plain"], "learned_time_to_target_s": tt["learned"],
+        "plain_median_s": med(tt["plain"]), "target_cost": target,
+        "hidden_params_cost": hidden_cost, "plain_time_to_hidden_s": th["plain"],
+        "learned_time_to_hidden_s": th["learned"], "final_best": finals,
+        "schedule_stage_kernel_s": total, "trace_collect_s": t_collect, "train_s": t_train,
+        "train_epoch_losses": losses, "improving_fraction": pos,
+    }
+    print(json.dumps(out), flush=True)
+    net.close()
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -154,6 +241,15 @@ def main() -> int:
                     help="c4 = the batched workload (256 uneven networks, one persistent launch per stage)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--mode", default="throughput", choices=["throughput", "learned"],
+                    help="learned: train the proposal network on c2 traces and compare time-to-target on c3")
+    ap.add_argument("--trace-rows", type=int, default=1 << 20)
+    ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--refresh", type=int, default=16)
+    ap.add_argument("--eps", type=float, default=0.1)
+    ap.add_argument("--eval-seeds", type=int, default=5)
+    ap.add_argument("--model-seed", type=int, default=2005)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB device buffer five times: the reference kernel of known "
                          "traffic that scales the HBM byte counters")
@@ -175,6 +271,8 @@ def main() -> int:
         print(json.dumps({"copy_bytes": nbytes, "copies": 5}), flush=True)
         return 0
     from paper_2506_19866_amd import sa, synth
+    if args.mode == "learned":
+        return bench_learned(args)
 
     name = args.workload
     if name == "c4":

@@ -57,6 +57,7 @@ enum { SA_HARD = 0, SA_PENALTY = 1 };
 
 typedef struct sa_problem sa_problem;
 typedef struct sa_run sa_run;
+typedef struct sa_mlp sa_mlp; /* proposal network, see the end of this header */
 
 /* A network, its experimental conditions and the reference data (§2.3, §2.5).
  * All pointers are host pointers, copied by sa_create_problem. */
@@ -131,9 +132,48 @@ typedef struct {
                                 0 = autotune (times the first stage with each, keeps the fastest) */
   int32_t use_graph;         /* non-zero: every sa_run_launch call becomes one captured hipGraph launch;
                                 excludes record_times */
+  /* Learned proposal and step trace (an extension of Table 1's GetCandidate,
+   * not in the paper).  Both need one problem, kernel SA_KERNEL_AUTO, at most
+   * 127 nodes and at most 42 observed times.  Before steps it = 0, R, 2R, ...
+   * of every stage a chain simulates its current vector once more and
+   * refreshes per-node aggregates of its observed-time states; with a model
+   * it also scores its 2P single-parameter moves from 32 features and builds
+   * integer weights floor(exp(score - max) * 2^16) (0 for moves that break
+   * a structural constraint in hard mode).  A learned step takes the first
+   * move whose cumulative weight exceeds (top 32 bits of Philox word 0 *
+   * total) >> 32, unless the top 32 bits of word 3 are below
+   * floor(eps_plain * 2^32) (eps_plain = 1: always), the weights are all 0,
+   * or the chain already holds that move's value: then it takes Table 1's
+   * candidate.  Constraints, simulation, score, Metropolis and restarts are
+   * those of the plain method. */
+  int32_t proposal;          /* SA_PROPOSAL_PLAIN or SA_PROPOSAL_LEARNED */
+  int32_t refresh_every;     /* R >= 1 (learned runs and traced runs) */
+  const sa_mlp *model;       /* learned: the scoring network; alive and unchanged while the run's work is queued */
+  double eps_plain;          /* learned: in [0, 1] */
+  void *trace_dev;           /* device, nullable: sa_trace_record [n_chains][trace_capacity] */
+  int64_t trace_capacity;    /* records per chain, >= 1 with trace_dev */
+  int32_t trace_every;       /* >= 1 with trace_dev: the steps whose global index g = k * L + it is a
+                                multiple of trace_every are recorded, in slot (g - g_first) / trace_every
+                                where g_first is the run's first such g; slots beyond the capacity are
+                                dropped.  Features use the aggregates of the chain's last refresh. */
 } sa_run_desc;
 
 enum { SA_KERNEL_AUTO = 0, SA_KERNEL_PERSISTENT = 1 };
+enum { SA_PROPOSAL_PLAIN = 0, SA_PROPOSAL_LEARNED = 1 };
+/* source of a candidate (trace flags bits 2-3) */
+enum { SA_SOURCE_PLAIN = 0, SA_SOURCE_LEARNED = 1, SA_SOURCE_STALE = 2, SA_SOURCE_EMPTY = 3 };
+
+/* One traced step: the candidate's 32 features (bfloat16 bit patterns; the
+ * feature definitions are those of the proposal network's inputs), the
+ * candidate (parameter index and new value), the cost change (0 when
+ * infeasible) and flags: bit 0 accepted, bit 1 feasible, bits 2-3 source. */
+typedef struct {
+  uint16_t features[32];
+  int32_t param;
+  int32_t value;
+  int32_t delta;
+  uint32_t flags;
+} sa_trace_record;
 
 typedef struct {
   int32_t n_probs;
@@ -192,6 +232,48 @@ int sa_chain_best(sa_run *run, int32_t prob, int32_t *cost_host, int8_t *x_host)
 int sa_stage_times(sa_run *run, int32_t prob, float *ms_host);
 
 int sa_destroy_run(sa_run *run);
+
+/* ---------------------------------------------------------------------------
+ * Learned proposal network.  An extension of Table 1's GetCandidate (not in
+ * the paper): a network scores every single-parameter move of a chain from 32
+ * features, and the learned run draws its candidates from those scores.
+ * Architecture: 32 inputs -> 256 ReLU units -> 1 score; bf16 weights and
+ * activations, float32 accumulation on the matrix cores.  Training: binary
+ * cross-entropy with logits, mean over the batch, Adam (beta1 0.9, beta2
+ * 0.999, eps 1e-8) on float32 master weights.
+ * All calls on one model use its internal scratch: queue them on one stream.
+ * ------------------------------------------------------------------------- */
+#define SA_MLP_INPUTS 32
+#define SA_MLP_HIDDEN 256
+#define SA_MLP_N_PARAMS (SA_MLP_INPUTS * SA_MLP_HIDDEN + SA_MLP_HIDDEN + 1)
+
+/* params (host, SA_MLP_N_PARAMS floats): W1[k][h] row-major (k < 32 inputs,
+ * h < 256 hidden units; input 31 is the constant 1, so W1[31][.] is the
+ * hidden bias), then w2[256], then b2.  Non-finite values give SA_ERR_DOMAIN.
+ * The model lives on the current device; creation synchronises the device. */
+int sa_mlp_create(const float *params, sa_mlp **out);
+int sa_mlp_destroy(sa_mlp *model);
+
+/* Copies the float32 master parameters to host (synchronises the device). */
+int sa_mlp_get_params(const sa_mlp *model, float *params);
+
+/* Replaces the parameters and resets the Adam state (synchronises the device). */
+int sa_mlp_set_params(sa_mlp *model, const float *params);
+
+/* Scores of n feature rows: x_dev [n][32] bfloat16 bit patterns (device),
+ * logit_dev [n] float (device).  n = 0 is a no-op. */
+int sa_mlp_forward(const sa_mlp *model, const uint16_t *x_dev, int64_t n, float *logit_dev, void *stream);
+
+/* Gradient of the batch's mean binary cross-entropy, labels y_dev [n] in
+ * [0, 1] (device): grad_dev [SA_MLP_N_PARAMS] floats in the layout of params
+ * (device); loss_dev (device, nullable) receives the mean loss.  n >= 1. */
+int sa_mlp_gradients(sa_mlp *model, const uint16_t *x_dev, const float *y_dev, int64_t n, float *grad_dev,
+                     float *loss_dev, void *stream);
+
+/* One Adam step with learning rate lr > 0 on the batch's gradient;
+ * loss_dev (device, nullable) receives the batch's mean loss before the step. */
+int sa_mlp_train_step(sa_mlp *model, const uint16_t *x_dev, const float *y_dev, int64_t n, float lr,
+                      float *loss_dev, void *stream);
 
 /* Message of the last failure on the calling thread ("" if none). */
 const char *sa_last_error(void);

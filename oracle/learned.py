@@ -142,27 +142,33 @@ def counts(prob, x):
     return np.bincount(dst[a == 1], minlength=N).tolist(), np.bincount(src[a != 0], minlength=N).tolist()
 
 
-def raises_violations(prob, p: int, old: int, v: int, ip, on) -> bool:
-    E = int(prob["n_edges"])
-    if p >= E:
-        return False
+def statics(prob) -> dict:
+    """Per-problem constants the features read: edge endpoints and degrees."""
+    N = int(prob["n_nodes"])
     src, dst = edge_list(prob)
-    j, i = int(src[p]), int(dst[p])
+    return {"src": src.tolist(), "dst": dst.tolist(), "E": int(prob["n_edges"]),
+            "indeg": np.diff(np.asarray(prob["row_ptr"], dtype=np.int64)).tolist(),
+            "outdeg": np.bincount(src, minlength=N).tolist()}
+
+
+def raises_violations(prob, p: int, old: int, v: int, ip, on, st=None) -> bool:
+    st = st or statics(prob)
+    if p >= st["E"]:
+        return False
+    j, i = st["src"][p], st["dst"][p]
     on_new = on[j] + (v != 0) - (old != 0)
     ip_new = ip[i] + (v == 1) - (old == 1)
     return (on_new == 0 and on[j] > 0) or (ip_new == 0 and ip[i] > 0)
 
 
-def move_features(prob, p: int, old: int, v: int, agg: dict, ip, on, lt) -> np.ndarray:
+def move_features(prob, p: int, old: int, v: int, agg: dict, ip, on, lt, st=None) -> np.ndarray:
     """The 32 float32 features of the move p: old -> v (definitions above)."""
-    N, E = int(prob["n_nodes"]), int(prob["n_edges"])
-    src, dst = edge_list(prob)
-    indeg = np.diff(np.asarray(prob["row_ptr"], dtype=np.int64))
-    outdeg = np.bincount(src, minlength=N)
+    st = st or statics(prob)
+    E, src, dst, indeg, outdeg = st["E"], st["src"], st["dst"], st["indeg"], st["outdeg"]
     f = np.zeros(N_FEATURES, dtype=np.float32)
     edge = p < E
-    i = int(dst[p]) if edge else p - E
-    j = int(src[p]) if edge else -1
+    i = dst[p] if edge else p - E
+    j = src[p] if edge else -1
     f[code(p, E, old)] = 1
     f[3 + code(p, E, v)] = 1
     f[6] = 0 if edge else 1
@@ -184,7 +190,7 @@ def move_features(prob, p: int, old: int, v: int, agg: dict, ip, on, lt) -> np.n
     f[17] = f32(indeg[i]) / f32(8)
     f[19] = lt
     f[20] = agg["mn"]
-    f[21] = 1 if raises_violations(prob, p, old, v, ip, on) else 0
+    f[21] = 1 if raises_violations(prob, p, old, v, ip, on, st) else 0
     f[22] = f32(ip[i]) / f32(8)
     f[31] = 1
     return f
@@ -217,7 +223,8 @@ def proposal_table(prob, x, T: float, model: dict) -> dict:
     agg = refresh_state(prob, x, T)
     hard = int(prob.get("hard", 1)) != 0
     moves = table_moves(prob, x)
-    X = np.stack([move_features(prob, p, old, v, agg, agg["ip"], agg["on"], agg["lt"]) for p, old, v in moves])
+    st = statics(prob)
+    X = np.stack([move_features(prob, p, old, v, agg, agg["ip"], agg["on"], agg["lt"], st) for p, old, v in moves])
     lg = logits(model, X)
     masked = (X[:, 21] != 0) & hard
     w = np.zeros(len(moves), dtype=np.uint64)
@@ -229,10 +236,11 @@ def proposal_table(prob, x, T: float, model: dict) -> dict:
 
 def run(prob, x0, *, seed: int, T0: float, rho: float, n_stages: int, steps_per_stage: int,
         model: dict | None, refresh: int, eps: float, first_stage: int = 0, net: int = 0,
-        trace_every: int = 0) -> dict:
+        trace_every: int = 0, first_chain: int = 0) -> dict:
     """Serial annealing with learned candidates (model None: plain candidates,
     with the refreshes still taken so that traced steps carry features).
-    Follows Table 1 for everything after the candidate is drawn."""
+    Follows Table 1 for everything after the candidate is drawn.  Chain c of
+    x0 draws as chain first_chain + c (a sample of a larger run)."""
     o = OracleProblem(prob)
     E, P = int(prob["n_edges"]), o.n_params
     hard = int(prob.get("hard", 1)) != 0
@@ -240,7 +248,8 @@ def run(prob, x0, *, seed: int, T0: float, rho: float, n_stages: int, steps_per_
     n = x0.shape[0]
     L = int(steps_per_stage)
     eps_u = eps_threshold(eps)
-    src, dst = edge_list(prob)
+    st = statics(prob)
+    src, dst = st["src"], st["dst"]
     start = [x0[c].copy() for c in range(n)]
     start_cost = [o.cost(x0[c]) for c in range(n)]
     out = {"stage_best": [], "stage_winner": [], "steps": [], "trace": []}
@@ -260,7 +269,7 @@ def run(prob, x0, *, seed: int, T0: float, rho: float, n_stages: int, steps_per_
                 if it % refresh == 0:
                     table = proposal_table(prob, x, T, model) if model is not None else None
                     agg = table["agg"] if table is not None else refresh_state(prob, x, T)
-                u = [int(w) for w in draw(seed, g, c, net)]
+                u = [int(w) for w in draw(seed, g, first_chain + c, net)]
                 top = [w >> 32 for w in u]
                 source = SOURCE_PLAIN
                 p = v = None
@@ -282,7 +291,7 @@ def run(prob, x0, *, seed: int, T0: float, rho: float, n_stages: int, steps_per_
                 old = int(x[p])
                 vc = vcur
                 if p < E:
-                    j, i = int(src[p]), int(dst[p])
+                    j, i = src[p], dst[p]
                     on_new = on[j] + int(v != 0) - int(old != 0)
                     ip_new = ip[i] + int(v == 1) - int(old == 1)
                     vc += int(on_new == 0) - int(on[j] == 0) + int(ip_new == 0) - int(ip[i] == 0)
@@ -295,7 +304,7 @@ def run(prob, x0, *, seed: int, T0: float, rho: float, n_stages: int, steps_per_
                     delta = cand - cur
                     accept = delta <= 0 or top[2] < threshold(T, delta)
                 if trace_every and g % trace_every == 0:
-                    f = move_features(prob, p, old, v, agg, ip, on, agg["lt"])
+                    f = move_features(prob, p, old, v, agg, ip, on, agg["lt"], st)
                     out["trace"].append((c, g, f, p, v, delta, int(accept) | (int(feasible) << 1) | (source << 2)))
                 out["steps"].append((c, g, source, p, v, int(feasible), delta, int(accept)))
                 if accept:

@@ -28,20 +28,25 @@ def bf16(a) -> np.ndarray:
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
-def forward(X, W1, b1, W2, b2):
+def forward(X, W1, b1, W2, b2, round_hidden=False):
+    """round_hidden: the hidden activations are rounded to bf16 before the
+    output layer, as the GPU network stores them (their gradient is then
+    taken straight through the rounding)."""
     Z = X @ W1 + b1
     H = np.maximum(Z, 0.0)
+    if round_hidden:
+        H = bf16(H)
     return Z, H, H @ W2 + b2
 
 
-def loss(X, y, W1, b1, W2, b2) -> float:
-    _, _, logit = forward(X, W1, b1, W2, b2)
+def loss(X, y, W1, b1, W2, b2, round_hidden=False) -> float:
+    _, _, logit = forward(X, W1, b1, W2, b2, round_hidden)
     return float(np.mean(np.logaddexp(0.0, logit) - y * logit))
 
 
-def grads(X, y, W1, b1, W2, b2) -> dict:
+def grads(X, y, W1, b1, W2, b2, round_hidden=False) -> dict:
     n = X.shape[0]
-    Z, H, logit = forward(X, W1, b1, W2, b2)
+    Z, H, logit = forward(X, W1, b1, W2, b2, round_hidden)
     dlogit = (1.0 / (1.0 + np.exp(-logit)) - y) / n
     dZ = np.outer(dlogit, W2) * (Z > 0)
     return {"W1": X.T @ dZ, "b1": dZ.sum(axis=0), "W2": H.T @ dlogit, "b2": float(dlogit.sum())}

@@ -1,6 +1,6 @@
 """Builds the HIP library libsa_anneal.so in-tree for gfx950 (hipcc).
 
-The two translation units compile in parallel; the shared library is linked
+The translation units compile in parallel; the shared library is linked
 next to this file so that the Python binding finds it without installation.
 """
 from __future__ import annotations
@@ -15,7 +15,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsa_anneal.so")
-SOURCES = ["sa_api.hip", "sa_k_batch.hip", "sa_k_stage.hip", "sa_k_persist.hip"]
+SOURCES = ["sa_api.hip", "sa_k_batch.hip", "sa_k_stage.hip", "sa_k_persist.hip", "sa_k_mlp.hip",
+           "sa_k_learned.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

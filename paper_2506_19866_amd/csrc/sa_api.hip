@@ -13,6 +13,7 @@
 
 #include "sa_anneal.h"
 #include "sa_internal.h"
+#include "sa_mlp.h"
 
 namespace {
 
@@ -83,7 +84,22 @@ struct sa_run {
   std::vector<hipEvent_t> ev_start, ev_stop;  // per stage, when record_times is set
   std::vector<hipGraphExec_t> graphs;
   hipStream_t capture_stream = nullptr;  // private stream the stages are captured on
+  bool learned = false;                  // learned proposal or trace: the learned-stage kernel
+  sa::LearnedArgs la{};                  // its stage-independent part
+  std::vector<float> lt;                 // per stage: f32(ln(T_k) / 5)
 };
+
+struct sa_mlp {
+  int device = 0;
+  float *master = nullptr, *m = nullptr, *v = nullptr;  // [kMlpParams] each
+  uint4 *w1f = nullptr, *w2f = nullptr;                 // bf16 fragments
+  float *partial = nullptr, *loss_partial = nullptr;    // [kMlpMaxWaves][kMlpParams], [kMlpMaxWaves]
+  int64_t steps = 0;                                    // Adam steps taken
+  void *dmem = nullptr;
+};
+
+static_assert(sizeof(sa_trace_record) == sizeof(sa::TraceRecord) && sizeof(sa_trace_record) == 80,
+              "trace record layout");
 
 extern "C" const char *sa_last_error(void) { return g_err.c_str(); }
 
@@ -270,6 +286,30 @@ extern "C" int sa_create_problem(const sa_problem_desc *d, sa_problem **out) {
         }
     }
 
+  // learned proposal: per-node slot and observation sums, per-parameter descriptor
+  std::vector<int16_t> node_slot(N);
+  std::vector<int32_t> node_sw(N, 0), node_wr(N, 0), indeg(N), outdeg(N);
+  for (int v = 0; v < N; ++v) {
+    node_slot[v] = (int16_t)(sg[v] * slots + sq[v]);
+    indeg[v] = d->in_row_ptr[v + 1] - d->in_row_ptr[v];
+    outdeg[v] = out_ptr[v + 1] - out_ptr[v];
+  }
+  for (int c = 0; c < C; ++c)
+    for (int k = 0; k < K; ++k)
+      for (int o = 0; o < O; ++o) {
+        const size_t at = ((size_t)c * K + k) * O + o;
+        node_sw[d->obs_nodes[o]] += W[at];
+        node_wr[d->obs_nodes[o]] += W[at] * d->observed[at];
+      }
+  std::vector<uint32_t> param_info(P);
+  for (int p = 0; p < P; ++p) {
+    const bool edge = p < E;
+    const int i = edge ? edst[p] : p - E, j = edge ? esrc[p] : 0;
+    param_info[p] = (uint32_t)(i & 127) | (uint32_t)(j & 127) << 7 | (uint32_t)(std::min(indeg[i], 127)) << 14 |
+                    (uint32_t)(edge ? std::min(outdeg[j], 127) : 0) << 21 | (uint32_t)edge << 28 |
+                    (uint32_t)(obs_index[i] >= 0) << 29 | (uint32_t)(edge && obs_index[j] >= 0) << 30;
+  }
+
   auto *pr = new sa_problem();
   hipGetDevice(&pr->device);
   Layout lay;
@@ -280,6 +320,8 @@ extern "C" int sa_create_problem(const sa_problem_desc *d, sa_problem **out) {
   const size_t o_b0 = lay.take(b0.size() * 4), o_cm = lay.take(cm.size() * 4);
   const size_t o_or = lay.take(orr.size() * 4), o_ow = lay.take(ow.size() * 4);
   const size_t o_obst = lay.take((size_t)K * 4), o_slot = lay.take(slot_node.size() * 2);
+  const size_t o_nslot = lay.take((size_t)N * 2), o_nsw = lay.take((size_t)N * 4), o_nwr = lay.take((size_t)N * 4);
+  const size_t o_pinfo = lay.take((size_t)P * 4);
   hipError_t e = hipMalloc(&pr->dmem, lay.bytes);
   if (e != hipSuccess) {
     delete pr;
@@ -302,6 +344,10 @@ extern "C" int sa_create_problem(const sa_problem_desc *d, sa_problem **out) {
   put(o_ow, ow.data(), ow.size() * 4);
   put(o_obst, d->obs_times, (size_t)K * 4);
   put(o_slot, slot_node.data(), slot_node.size() * 2);
+  put(o_nslot, node_slot.data(), (size_t)N * 2);
+  put(o_nsw, node_sw.data(), (size_t)N * 4);
+  put(o_nwr, node_wr.data(), (size_t)N * 4);
+  put(o_pinfo, param_info.data(), (size_t)P * 4);
   e = hipMemcpy(pr->dmem, host.data(), lay.bytes, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     hipFree(pr->dmem);
@@ -327,6 +373,11 @@ extern "C" int sa_create_problem(const sa_problem_desc *d, sa_problem **out) {
   dp.obs_w = (const uint32_t *)(base + o_ow);
   dp.obs_t = (const int32_t *)(base + o_obst);
   dp.slot_node = (const int16_t *)(base + o_slot);
+  dp.sum_w = (int32_t)wsum;
+  dp.node_slot = (const int16_t *)(base + o_nslot);
+  dp.node_sw = (const int32_t *)(base + o_nsw);
+  dp.node_wr = (const int32_t *)(base + o_nwr);
+  dp.param_info = (const uint32_t *)(base + o_pinfo);
 
   sa_problem_info &in = pr->info;
   in.n_params = P; in.n_nodes = N; in.n_edges = E; in.n_conditions = C; in.n_steps = T;
@@ -475,7 +526,13 @@ static int enqueue_stage(sa_run *r, int32_t st, hipStream_t stream) {
     a.xbest = r->xbest;
     a.cbest = r->cbest;
     a.cstats = r->cstats;
-    SA_HIP((hipError_t)sa::launch_stage(pb, a, stream), "stage launch");
+    if (r->learned) {
+      sa::LearnedArgs la = r->la;
+      la.lt = r->lt[st];
+      SA_HIP((hipError_t)sa::launch_learned_stage(pb, a, la, stream), "learned stage launch");
+    } else {
+      SA_HIP((hipError_t)sa::launch_stage(pb, a, stream), "stage launch");
+    }
   } else {
     for (size_t k = 0; k < r->item_class_d.size(); ++k) {
       sa::BatchArgs a{};
@@ -579,6 +636,24 @@ extern "C" int sa_run_create(sa_problem *const *probs, int32_t n_probs, const sa
       desc->chains_per_block != 4 && desc->chains_per_block != 8)
     return fail(SA_ERR_ARG, "chains_per_block must be 0 (autotune), 1, 2, 4 or 8");
   if (desc->record_times && desc->use_graph) return fail(SA_ERR_ARG, "record_times and use_graph exclude each other");
+  const bool learned = desc->proposal == SA_PROPOSAL_LEARNED, traced = desc->trace_dev != nullptr;
+  if (desc->proposal != SA_PROPOSAL_PLAIN && !learned) return fail(SA_ERR_ARG, "unknown proposal %d", desc->proposal);
+  if (learned && !desc->model) return fail(SA_ERR_ARG, "the learned proposal needs a model");
+  if ((learned || traced) && desc->refresh_every < 1) return fail(SA_ERR_ARG, "refresh_every must be >= 1");
+  if (learned && !(desc->eps_plain >= 0.0 && desc->eps_plain <= 1.0))
+    return fail(SA_ERR_ARG, "eps_plain must be in [0, 1]");
+  if (traced && (desc->trace_every < 1 || desc->trace_capacity < 1))
+    return fail(SA_ERR_ARG, "trace_every and trace_capacity must be >= 1");
+  if (learned || traced) {
+    if (n_probs != 1 || desc->kernel != SA_KERNEL_AUTO)
+      return fail(SA_ERR_UNSUPPORTED, "the learned proposal and the trace run one problem on the specialised kernel");
+    const sa::DevProblem &dp = probs[0]->dev;
+    if (dp.nm > sa::kLearnedMaxTilesM)
+      return fail(SA_ERR_UNSUPPORTED, "learned proposal / trace: %d nodes (at most 127)", dp.N);
+    if (dp.K > sa::kLearnedMaxObsTimes)
+      return fail(SA_ERR_UNSUPPORTED, "learned proposal / trace: %d observed times (at most 42)", dp.K);
+    if (learned && desc->model->device != probs[0]->device) return fail(SA_ERR_ARG, "model on another device");
+  }
   const int device = probs[0]->device;
   for (int i = 1; i < n_probs; ++i)
     if (probs[i]->device != device) return fail(SA_ERR_ARG, "problems on different devices");
@@ -608,7 +683,36 @@ extern "C" int sa_run_create(sa_problem *const *probs, int32_t n_probs, const sa
     wo += probs[i]->dev.P;
     max_cost = std::max(max_cost, probs[i]->info.max_cost);
   }
-  if (!persistent) {
+  if (learned || traced) {
+    r->learned = true;
+    const size_t smem = sa::learned_smem_bytes(probs[0]->dev, learned);
+    if (smem > 160 * 1024) {
+      free_run(r);
+      return fail(SA_ERR_UNSUPPORTED, "learned stage kernel needs %zu bytes of LDS", smem);
+    }
+    hipError_t pe = (hipError_t)sa::learned_stage_prepare(probs[0]->dev, smem);
+    if (pe != hipSuccess) {
+      free_run(r);
+      return hip_fail(pe, "learned stage LDS limit");
+    }
+    sa::LearnedArgs &la = r->la;
+    la.refresh = desc->refresh_every;
+    if (learned) {
+      la.w1f = desc->model->w1f;
+      la.w2f = desc->model->w2f;
+      la.b2 = desc->model->master + sa::kMlpParams - 1;
+      la.eps_u = desc->eps_plain >= 1.0 ? (1ull << 32)
+                                        : std::min<uint64_t>((uint64_t)std::floor(desc->eps_plain * 4294967296.0),
+                                                             0xFFFFFFFFull);
+    }
+    if (traced) {
+      la.trace = static_cast<sa::TraceRecord *>(desc->trace_dev);
+      la.trace_cap = desc->trace_capacity;
+      la.trace_every = desc->trace_every;
+      const int64_t g0 = (int64_t)desc->first_stage * desc->steps_per_stage;
+      la.trace_first = (g0 + desc->trace_every - 1) / desc->trace_every * desc->trace_every;
+    }
+  } else if (!persistent) {
     const size_t smem = sa::stage_smem_bytes(probs[0]->dev, sa::stage_waves_per_block(probs[0]->dev));
     if (smem > 64 * 1024) {
       free_run(r);
@@ -645,6 +749,7 @@ extern "C" int sa_run_create(sa_problem *const *probs, int32_t n_probs, const sa
     tau_table(T, max_cost, tab, cap);
     r->tau_off.push_back(all_tau.size());
     r->dcap.push_back(cap);
+    r->lt.push_back((float)(std::log(T) / 5.0));
     all_tau.insert(all_tau.end(), tab.begin(), tab.end());
     T = T * desc->rho;
   }
@@ -862,5 +967,166 @@ extern "C" int sa_destroy_run(sa_run *r) {
   hipSetDevice(r->device);
   hipStreamSynchronize(r->stream);
   free_run(r);
+  return SA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// proposal network
+// ---------------------------------------------------------------------------
+
+static int mlp_check_params(const float *params) {
+  if (!params) return fail(SA_ERR_ARG, "params is NULL");
+  for (int i = 0; i < sa::kMlpParams; ++i)
+    if (!std::isfinite(params[i])) return fail(SA_ERR_DOMAIN, "params[%d] is not finite", i);
+  return SA_OK;
+}
+
+static int mlp_upload(sa_mlp *m, const float *params) {
+  SA_HIP(hipSetDevice(m->device), "hipSetDevice");
+  SA_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  SA_HIP(hipMemcpy(m->master, params, sizeof(float) * sa::kMlpParams, hipMemcpyHostToDevice), "copy params");
+  SA_HIP(hipMemset(m->m, 0, sizeof(float) * sa::kMlpParams), "clear Adam state");
+  SA_HIP(hipMemset(m->v, 0, sizeof(float) * sa::kMlpParams), "clear Adam state");
+  m->steps = 0;
+  sa::MlpUpdateArgs u{};
+  u.master = m->master;
+  u.w1f = m->w1f;
+  u.w2f = m->w2f;
+  SA_HIP(sa::launch_mlp_update(u, nullptr), "pack fragments");
+  SA_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  return SA_OK;
+}
+
+extern "C" int sa_mlp_create(const float *params, sa_mlp **out) {
+  if (!out) return fail(SA_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (int rc = mlp_check_params(params)) return rc;
+  auto *m = new sa_mlp();
+  hipGetDevice(&m->device);
+  Layout lay;
+  const size_t o_master = lay.take(sizeof(float) * sa::kMlpParams), o_m = lay.take(sizeof(float) * sa::kMlpParams),
+               o_v = lay.take(sizeof(float) * sa::kMlpParams), o_w1f = lay.take(sizeof(uint4) * sa::kW1FragU4),
+               o_w2f = lay.take(sizeof(uint4) * sa::kW2FragU4),
+               o_part = lay.take(sizeof(float) * sa::kMlpParams * (size_t)sa::kMlpMaxWaves),
+               o_loss = lay.take(sizeof(float) * sa::kMlpMaxWaves);
+  hipError_t e = hipMalloc(&m->dmem, lay.bytes);
+  if (e != hipSuccess) {
+    delete m;
+    return hip_fail(e, "hipMalloc(model)");
+  }
+  char *base = static_cast<char *>(m->dmem);
+  m->master = reinterpret_cast<float *>(base + o_master);
+  m->m = reinterpret_cast<float *>(base + o_m);
+  m->v = reinterpret_cast<float *>(base + o_v);
+  m->w1f = reinterpret_cast<uint4 *>(base + o_w1f);
+  m->w2f = reinterpret_cast<uint4 *>(base + o_w2f);
+  m->partial = reinterpret_cast<float *>(base + o_part);
+  m->loss_partial = reinterpret_cast<float *>(base + o_loss);
+  if (int rc = mlp_upload(m, params)) {
+    hipFree(m->dmem);
+    delete m;
+    return rc;
+  }
+  *out = m;
+  return SA_OK;
+}
+
+extern "C" int sa_mlp_destroy(sa_mlp *m) {
+  if (!m) return SA_OK;
+  hipSetDevice(m->device);
+  hipDeviceSynchronize();
+  hipFree(m->dmem);
+  delete m;
+  return SA_OK;
+}
+
+extern "C" int sa_mlp_get_params(const sa_mlp *m, float *params) {
+  if (!m || !params) return fail(SA_ERR_ARG, "NULL model or params");
+  SA_HIP(hipSetDevice(m->device), "hipSetDevice");
+  SA_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  SA_HIP(hipMemcpy(params, m->master, sizeof(float) * sa::kMlpParams, hipMemcpyDeviceToHost), "copy params");
+  return SA_OK;
+}
+
+extern "C" int sa_mlp_set_params(sa_mlp *m, const float *params) {
+  if (!m) return fail(SA_ERR_ARG, "model is NULL");
+  if (int rc = mlp_check_params(params)) return rc;
+  return mlp_upload(m, params);
+}
+
+extern "C" int sa_mlp_forward(const sa_mlp *m, const uint16_t *x, int64_t n, float *logit, void *stream) {
+  if (!m || n < 0) return fail(SA_ERR_ARG, "NULL model or negative n");
+  if (n == 0) return SA_OK;
+  if (!x || !logit) return fail(SA_ERR_ARG, "NULL x or logit");
+  SA_HIP(sa::launch_mlp_forward(reinterpret_cast<const uint4 *>(x), n, logit, m->w1f, m->w2f, m->master,
+                                (hipStream_t)stream),
+         "mlp forward");
+  return SA_OK;
+}
+
+static int mlp_backward(sa_mlp *m, const uint16_t *x, const float *y, int64_t n, hipStream_t s, int &waves) {
+  const int64_t tiles = (n + 31) / 32;
+  int64_t w = std::min<int64_t>(tiles, sa::kMlpMaxWaves);
+  const int64_t tpw = (tiles + w - 1) / w;
+  w = (tiles + tpw - 1) / tpw;
+  if (tpw > INT32_MAX) return fail(SA_ERR_ARG, "batch too large");
+  sa::MlpTrainArgs a{};
+  a.x = reinterpret_cast<const uint4 *>(x);
+  a.y = y;
+  a.n = n;
+  a.tiles_per_wave = (int)tpw;
+  a.waves = (int)w;
+  a.master = m->master;
+  a.w1f = m->w1f;
+  a.partial = m->partial;
+  a.loss_partial = m->loss_partial;
+  SA_HIP(sa::launch_mlp_train(a, s), "mlp forward/backward");
+  waves = (int)w;
+  return SA_OK;
+}
+
+extern "C" int sa_mlp_gradients(sa_mlp *m, const uint16_t *x, const float *y, int64_t n, float *grad,
+                                float *loss, void *stream) {
+  if (!m || !x || !y || !grad || n < 1) return fail(SA_ERR_ARG, "NULL argument or n < 1");
+  int waves = 0;
+  if (int rc = mlp_backward(m, x, y, n, (hipStream_t)stream, waves)) return rc;
+  sa::MlpUpdateArgs u{};
+  u.partial = m->partial;
+  u.loss_partial = m->loss_partial;
+  u.waves = waves;
+  u.grad_out = grad;
+  u.loss_out = loss;
+  u.master = m->master;
+  u.w1f = m->w1f;
+  u.w2f = m->w2f;
+  SA_HIP(sa::launch_mlp_update(u, (hipStream_t)stream), "mlp gradient reduction");
+  return SA_OK;
+}
+
+extern "C" int sa_mlp_train_step(sa_mlp *m, const uint16_t *x, const float *y, int64_t n, float lr, float *loss,
+                                 void *stream) {
+  if (!m || !x || !y || n < 1) return fail(SA_ERR_ARG, "NULL argument or n < 1");
+  if (!(lr > 0.f) || !std::isfinite(lr)) return fail(SA_ERR_ARG, "lr must be positive");
+  int waves = 0;
+  if (int rc = mlp_backward(m, x, y, n, (hipStream_t)stream, waves)) return rc;
+  m->steps += 1;
+  sa::MlpUpdateArgs u{};
+  u.partial = m->partial;
+  u.loss_partial = m->loss_partial;
+  u.waves = waves;
+  u.loss_out = loss;
+  u.adam = 1;
+  u.lr = lr;
+  u.beta1 = 0.9f;
+  u.beta2 = 0.999f;
+  u.eps = 1e-8f;
+  u.bc1 = (float)(1.0 - std::pow(0.9, (double)m->steps));
+  u.bc2 = (float)(1.0 - std::pow(0.999, (double)m->steps));
+  u.master = m->master;
+  u.m = m->m;
+  u.v = m->v;
+  u.w1f = m->w1f;
+  u.w2f = m->w2f;
+  SA_HIP(sa::launch_mlp_update(u, (hipStream_t)stream), "mlp Adam step");
   return SA_OK;
 }

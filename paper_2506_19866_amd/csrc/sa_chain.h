@@ -28,9 +28,20 @@ struct ChainJob {
   const uint32_t *tau;    // thresholds of this stage, [dcap + 1]
 };
 
-template <int NM, int NK, int D, bool RT>
+// Hooks of the learned proposal (see sa_learned.h).  The plain method passes
+// NoHooks, whose calls compile away.
+//   refresh(A, it, ...)   before step it: rebuild the proposal table
+//   select(...)           pick the candidate from the table, or decline
+//   record(...)           after the decision, before the chain moves
+// Sources of a candidate: 0 plain draw, 1 table, 2 plain because the table's
+// move repeats the current value, 3 plain because the table is empty.
+struct NoHooks {
+  static constexpr bool kEnabled = false;
+};
+
+template <int NM, int NK, int D, bool RT, class Hooks = NoHooks>
 __device__ __forceinline__ void run_chain(const DevProblem &pb, const ChainJob &job, int lane, uint8_t *lds,
-                                          const uint32_t *lds_r, const uint32_t *lds_w) {
+                                          const uint32_t *lds_r, const uint32_t *lds_w, Hooks *hk = nullptr) {
   const int P = pb.P, E = pb.E;
   const int P4 = round4(P), N4 = round4(pb.N);
   uint8_t *xcur = lds;
@@ -59,13 +70,22 @@ __device__ __forceinline__ void run_chain(const DevProblem &pb, const ChainJob &
       const uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane((int)dr.w0, j);
       const uint32_t r1 = (uint32_t)__builtin_amdgcn_readlane((int)dr.w1, j);
       const uint32_t r2 = (uint32_t)__builtin_amdgcn_readlane((int)dr.w2, j);
-      // GetCandidate (Table 1): uniform index, one of the two other values
-      const int p = (int)(((uint64_t)r0 * (uint64_t)P) >> 32);
+      int p, nv, source = 0;
+      bool chosen = false;
+      if constexpr (Hooks::kEnabled) {
+        hk->refresh(A, it0 + j, xcur, outnz, inplus, ccur, vcur, lane, lds_r, lds_w);
+        const uint32_t r3 = (uint32_t)__builtin_amdgcn_readlane((int)dr.w3, j);
+        chosen = hk->select(r0, r3, xcur, p, nv, source, lane);
+      }
+      if (!chosen) {
+        // GetCandidate (Table 1): uniform index, one of the two other values
+        p = (int)(((uint64_t)r0 * (uint64_t)P) >> 32);
+        const int cur = uniform((int)(int8_t)xcur[p]);
+        const int ncode = ((p < E ? cur + 1 : cur) + 1 + (int)(r1 >> 31)) % 3;
+        nv = p < E ? ncode - 1 : ncode;
+      }
       const int old = uniform((int)(int8_t)xcur[p]);
       const bool is_edge = p < E;
-      const int code = is_edge ? old + 1 : old;
-      const int ncode = (code + 1 + (int)(r1 >> 31)) % 3;
-      const int nv = is_edge ? ncode - 1 : ncode;
       // structural constraints (§2.5.3) from the per-node counts
       int vc = vcur, src = 0, dst = 0, on_new = 0, ip_new = 0;
       if (is_edge) {
@@ -94,6 +114,8 @@ __device__ __forceinline__ void run_chain(const DevProblem &pb, const ChainJob &
       // Metropolis in fixed point: accept iff delta <= 0 or u32 < tau[delta]
       const bool accept = feasible && (delta <= 0 || (delta <= job.dcap && r2 < job.tau[delta]));
       patch_a(A, reg, accept ? 0u : mask, ((uint32_t)(is_edge ? old : -old) & 0xffu) * kLowBits);
+      if constexpr (Hooks::kEnabled)
+        hk->record(job.g0 + (uint64_t)(it0 + j), p, old, nv, feasible, delta, accept, source, outnz, inplus, lane);
       if (!feasible) {
         ++n_inf;  // infeasible candidate (§2.5.3): a rejected step, no redraw
       } else if (accept) {

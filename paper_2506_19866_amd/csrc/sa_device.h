@@ -47,10 +47,11 @@ __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirs
 // Philox4x64-10 (Salmon et al., SC'11): ten rounds of two 64x64->128
 // multiplications by the Philox constants, the high halves mixed with the
 // other two words and the round key, the key advanced by the Weyl constants.
-// Returns the top 32 bits of words 0, 1 and 2 (the only bits a step uses).
+// Returns the top 32 bits of the four words (the only bits a step uses; the
+// plain proposal uses words 0-2, and the compiler drops word 3 there).
 // ---------------------------------------------------------------------------
 struct Draw {
-  uint32_t w0, w1, w2;
+  uint32_t w0, w1, w2, w3;
 };
 
 __device__ __forceinline__ Draw philox_top_words(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
@@ -71,7 +72,7 @@ __device__ __forceinline__ Draw philox_top_words(uint64_t c0, uint64_t c1, uint6
     c2 = n2;
     c3 = lo0;
   }
-  return {(uint32_t)(c0 >> 32), (uint32_t)(c1 >> 32), (uint32_t)(c2 >> 32)};
+  return {(uint32_t)(c0 >> 32), (uint32_t)(c1 >> 32), (uint32_t)(c2 >> 32), (uint32_t)(c3 >> 32)};
 }
 
 // ---------------------------------------------------------------------------
@@ -289,6 +290,18 @@ __device__ __forceinline__ void time_step(const ATile<NM, NK> &A, const v4i (&B)
     constexpr int q = decltype(qc)::value;
     if constexpr (q >= NM) NB[q >> 2][q & 3] = B[q >> 2][q & 3];
   });
+  if constexpr (!RT) {
+    // keep the whole step in one block and let the m-tiles' integer work run
+    // under the next m-tile's matrix products
+#pragma unroll
+    for (int kt = 0; kt < NK; ++kt) asm volatile("" : "+v"(NB[kt]));
+    __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+    static_for<NM - 1>([&](auto) SA_INLINE {
+      __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, 10, 0);
+    });
+    __builtin_amdgcn_sched_group_barrier(0x002, 12, 0);
+  }
 }
 
 // Simulates every condition for the chain whose parameters are in A and

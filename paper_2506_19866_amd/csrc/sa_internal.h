@@ -51,6 +51,13 @@ struct DevProblem {
   const uint32_t *obs_r, *obs_w;
   const int32_t *obs_t;                // [K]
   const int16_t *slot_node;            // [4][16*nk]: node at (g, q), -1 bias/empty
+  // learned proposal (networks up to 127 nodes)
+  int32_t sum_w;                       // sum of all observation weights
+  const int16_t *node_slot;            // [N]: g * 16*nk + q of the node's slot
+  const int32_t *node_sw, *node_wr;    // [N]: sum of W and of W*R over the node's observations (0: unobserved)
+  // [P]: target i | source j << 7 | in-degree(i) << 14 | out-degree(j) << 21 |
+  // edge << 28 | observed(i) << 29 | observed(j) << 30 (j = 0 for a threshold)
+  const uint32_t *param_info;
 };
 
 // One temperature stage of one problem.
@@ -116,8 +123,28 @@ struct BatchReduceArgs {
   uint32_t *queue;            // [2] work counters to reset, or null
 };
 
-// Launch wrappers (sa_k_batch.hip, sa_k_stage.hip, sa_k_persist.hip).  All
-// return a hipError_t as int.
+// One traced annealing step (the C ABI's sa_trace_record).
+struct TraceRecord {
+  uint16_t features[32];  // bf16 features of the candidate (refresh-time aggregates, current vector)
+  int32_t param, value, delta;
+  uint32_t flags;         // bit 0 accepted, bit 1 feasible, bits 2-3 source
+};
+
+// The learned proposal's part of a stage (sa_k_learned.hip).
+struct LearnedArgs {
+  const void *w1f, *w2f;   // bf16 network fragments; null: plain candidates, refreshes only for the trace
+  const float *b2;         // device scalar
+  int32_t refresh;         // steps between table refreshes
+  uint64_t eps_u;          // the plain candidate is taken when Philox word 3's top 32 bits are below this
+  float lt;                // f32(ln(T_k) / 5) of the stage
+  TraceRecord *trace;      // [n_chains][trace_cap] or null
+  int64_t trace_cap;
+  int64_t trace_every;
+  int64_t trace_first;     // first traced global step of the run
+};
+
+// Launch wrappers (sa_k_batch.hip, sa_k_stage.hip, sa_k_persist.hip,
+// sa_k_learned.hip).  All return a hipError_t as int.
 int launch_eval(const DevProblem &pb, const int8_t *x, int64_t n, int32_t *cost, void *stream);
 int launch_simulate(const DevProblem &pb, const int8_t *x, int64_t n, int8_t *traj, void *stream);
 int launch_stage(const DevProblem &pb, const StageArgs &sa, void *stream);
@@ -129,5 +156,11 @@ size_t persistent_smem_bytes(const DevProblem &pb, int waves);
 // Workgroups of `waves` waves with `smem` bytes of LDS that fit on one CU.
 int persistent_blocks_per_cu(int waves, size_t smem);
 constexpr int kPersistentTilesM = 10, kPersistentTilesK = 3;  // networks up to 159 nodes
+int launch_learned_stage(const DevProblem &pb, const StageArgs &sa, const LearnedArgs &la, void *stream);
+// LDS of a learned-stage workgroup; prepare sets the kernel's LDS limit to it.
+size_t learned_smem_bytes(const DevProblem &pb, bool model);
+int learned_stage_prepare(const DevProblem &pb, size_t smem);
+constexpr int kLearnedMaxTilesM = 8;      // networks up to 127 nodes
+constexpr int kLearnedMaxObsTimes = 42;   // byte accumulators of the refresh aggregates
 
 }  // namespace sa

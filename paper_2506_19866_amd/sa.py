@@ -19,10 +19,20 @@ SA_ERR_ARG, SA_ERR_DOMAIN, SA_ERR_TOPOLOGY, SA_ERR_INFEASIBLE = -1, -2, -3, -4
 SA_ERR_DEVICE, SA_ERR_OOM, SA_ERR_UNSUPPORTED, SA_ERR_OVERFLOW = -5, -6, -7, -8
 SA_HARD, SA_PENALTY = 0, 1
 SA_KERNEL_AUTO, SA_KERNEL_PERSISTENT = 0, 1
+SA_PROPOSAL_PLAIN, SA_PROPOSAL_LEARNED = 0, 1
+SA_SOURCE_PLAIN, SA_SOURCE_LEARNED, SA_SOURCE_STALE, SA_SOURCE_EMPTY = 0, 1, 2, 3
+TRACE_RECORD_BYTES = 80
+# sa_trace_record: 32 bf16 feature bit patterns, candidate, cost change, flags
+TRACE_DTYPE = np.dtype([("features", "<u2", (32,)), ("param", "<i4"), ("value", "<i4"), ("delta", "<i4"),
+                        ("flags", "<u4")])
 
 EXPORTS = ("sa_create_problem", "sa_destroy_problem", "sa_problem_get_info", "sa_eval_cost",
            "sa_simulate", "sa_run_create", "sa_run_launch", "sa_run_chains", "sa_best", "sa_stats",
-           "sa_chain_best", "sa_stage_times", "sa_run_get_info", "sa_destroy_run", "sa_last_error")
+           "sa_chain_best", "sa_stage_times", "sa_run_get_info", "sa_destroy_run", "sa_mlp_create",
+           "sa_mlp_destroy", "sa_mlp_get_params", "sa_mlp_set_params", "sa_mlp_forward", "sa_mlp_gradients",
+           "sa_mlp_train_step", "sa_last_error")
+MLP_INPUTS, MLP_HIDDEN = 32, 256
+MLP_N_PARAMS = MLP_INPUTS * MLP_HIDDEN + MLP_HIDDEN + 1
 
 
 class SAError(RuntimeError):
@@ -56,6 +66,8 @@ class _RunDesc(C.Structure):
         ("first_stage", C.c_int32), ("n_stages", C.c_int32), ("steps_per_stage", C.c_int32),
         ("record_times", C.c_int32), ("kernel", C.c_int32), ("chains_per_block", C.c_int32),
         ("use_graph", C.c_int32),
+        ("proposal", C.c_int32), ("refresh_every", C.c_int32), ("model", C.c_void_p), ("eps_plain", C.c_double),
+        ("trace_dev", C.c_void_p), ("trace_capacity", C.c_int64), ("trace_every", C.c_int32),
     ]
 
 
@@ -97,6 +109,13 @@ def lib():
         L.sa_stage_times.argtypes = [vp, C.c_int32, vp]
         L.sa_run_get_info.argtypes = [vp, C.POINTER(_RunInfo)]
         L.sa_destroy_run.argtypes = [vp]
+        L.sa_mlp_create.argtypes = [vp, C.POINTER(vp)]
+        L.sa_mlp_destroy.argtypes = [vp]
+        L.sa_mlp_get_params.argtypes = [vp, vp]
+        L.sa_mlp_set_params.argtypes = [vp, vp]
+        L.sa_mlp_forward.argtypes = [vp, vp, C.c_int64, vp, vp]
+        L.sa_mlp_gradients.argtypes = [vp, vp, vp, C.c_int64, vp, vp, vp]
+        L.sa_mlp_train_step.argtypes = [vp, vp, vp, C.c_int64, C.c_float, vp, vp]
         L.sa_last_error.restype = C.c_char_p
         for name in EXPORTS:
             if name != "sa_last_error":
@@ -211,9 +230,13 @@ class Run:
     def __init__(self, problems, x0, *, seed: int, T0: float, rho: float, n_stages: int,
                  steps_per_stage: int, first_stage: int = 0, stream=None, launch: bool = True,
                  record_times: bool = False, kernel: int = SA_KERNEL_AUTO, chains_per_block: int = 0,
-                 use_graph: bool = False):
+                 use_graph: bool = False, model: "Mlp | None" = None, refresh_every: int = 16,
+                 eps_plain: float = 0.1, trace=None, trace_every: int = 1):
         """problems: a Problem or a list of them; x0: int8 CUDA tensor [n_chains, P]
-        for one problem, or a list (one [n_chains, P_p] tensor per problem)."""
+        for one problem, or a list (one [n_chains, P_p] tensor per problem).
+        model: learned proposal with this network; trace: uint8 CUDA tensor
+        [n_chains, capacity * 80] receiving sa_trace_record rows (decode with
+        decode_trace)."""
         import torch
         if isinstance(problems, Problem):
             problems, x0 = [problems], [x0]
@@ -227,9 +250,18 @@ class Run:
         self.n_chains = n
         self.n_stages = n_stages
         self.launched = 0
+        trace_ptr, cap = None, 0
+        if trace is not None:
+            trace = _device_tensor(trace, torch.uint8)
+            if trace.dim() != 2 or trace.shape[0] != n or trace.shape[1] % TRACE_RECORD_BYTES:
+                raise ValueError("trace must be uint8 [n_chains, capacity * 80]")
+            trace_ptr, cap = trace.data_ptr(), trace.shape[1] // TRACE_RECORD_BYTES
+        self._trace, self.model = trace, model
         d = _RunDesc(n, int(seed) & (2**64 - 1), float(T0), float(rho), int(first_stage), int(n_stages),
                      int(steps_per_stage), 1 if record_times else 0, int(kernel), int(chains_per_block),
-                     1 if use_graph else 0)
+                     1 if use_graph else 0, SA_PROPOSAL_LEARNED if model is not None else SA_PROPOSAL_PLAIN,
+                     int(refresh_every), model.handle if model is not None else None, float(eps_plain),
+                     trace_ptr, int(cap), int(trace_every))
         probs = (C.c_void_p * len(self.problems))(*[p.handle for p in self.problems])
         h = C.c_void_p()
         _check(lib().sa_run_create(probs, len(self.problems), C.byref(d), C.c_void_p(self._x0.data_ptr()),
@@ -282,3 +314,101 @@ class Run:
             self.close()
         except Exception:
             pass
+
+
+def pack_mlp_params(W1, w2, b2) -> np.ndarray:
+    """Flat float32 parameter array: W1 [32][256] row-major (row 31 is the
+    hidden bias, fed by the constant input 31), w2 [256], b2."""
+    W1 = np.asarray(W1, dtype=np.float32).reshape(MLP_INPUTS, MLP_HIDDEN)
+    w2 = np.asarray(w2, dtype=np.float32).reshape(MLP_HIDDEN)
+    return np.concatenate([W1.reshape(-1), w2, np.asarray([b2], dtype=np.float32)])
+
+
+def unpack_mlp_params(flat) -> dict:
+    flat = np.asarray(flat, dtype=np.float32)
+    nw = MLP_INPUTS * MLP_HIDDEN
+    return {"W1": flat[:nw].reshape(MLP_INPUTS, MLP_HIDDEN).copy(), "w2": flat[nw:nw + MLP_HIDDEN].copy(),
+            "b2": float(flat[-1])}
+
+
+class Mlp:
+    """The proposal network (32 -> 256 ReLU -> 1) on the current HIP device.
+    Feature rows are torch.bfloat16 tensors [n, 32]; labels float32 [n]."""
+
+    def __init__(self, params):
+        flat = np.ascontiguousarray(params, dtype=np.float32).reshape(-1)
+        if flat.size != MLP_N_PARAMS:
+            raise ValueError(f"expected {MLP_N_PARAMS} parameters, got {flat.size}")
+        h = C.c_void_p()
+        _check(lib().sa_mlp_create(flat.ctypes.data, C.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def params(self) -> np.ndarray:
+        out = np.empty(MLP_N_PARAMS, dtype=np.float32)
+        _check(lib().sa_mlp_get_params(self._h, out.ctypes.data))
+        return out
+
+    def set_params(self, params) -> None:
+        flat = np.ascontiguousarray(params, dtype=np.float32).reshape(-1)
+        if flat.size != MLP_N_PARAMS:
+            raise ValueError(f"expected {MLP_N_PARAMS} parameters, got {flat.size}")
+        _check(lib().sa_mlp_set_params(self._h, flat.ctypes.data))
+
+    def forward(self, x, stream=None):
+        import torch
+        x = _device_tensor(x, torch.bfloat16, MLP_INPUTS)
+        out = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+        _check(lib().sa_mlp_forward(self._h, x.data_ptr(), x.shape[0], out.data_ptr(), _stream_handle(stream)))
+        return out
+
+    def gradients(self, x, y, stream=None):
+        import torch
+        x = _device_tensor(x, torch.bfloat16, MLP_INPUTS)
+        y = _device_tensor(y, torch.float32)
+        if y.dim() != 1 or y.shape[0] != x.shape[0]:
+            raise ValueError("labels must be [n]")
+        grad = torch.empty(MLP_N_PARAMS, dtype=torch.float32, device=x.device)
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        _check(lib().sa_mlp_gradients(self._h, x.data_ptr(), y.data_ptr(), x.shape[0], grad.data_ptr(),
+                                      loss.data_ptr(), _stream_handle(stream)))
+        return grad, loss
+
+    def train_step(self, x, y, lr: float, stream=None, loss=None):
+        """One Adam step; returns the device scalar holding the batch's loss."""
+        import torch
+        x = _device_tensor(x, torch.bfloat16, MLP_INPUTS)
+        y = _device_tensor(y, torch.float32)
+        if y.dim() != 1 or y.shape[0] != x.shape[0]:
+            raise ValueError("labels must be [n]")
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        _check(lib().sa_mlp_train_step(self._h, x.data_ptr(), y.data_ptr(), x.shape[0], float(lr),
+                                       loss.data_ptr(), _stream_handle(stream)))
+        return loss
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().sa_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def decode_trace(trace) -> np.ndarray:
+    """sa_trace_record rows of a trace tensor [n_chains, capacity * 80] as a
+    numpy structured array [n_chains, capacity] (features as float32)."""
+    raw = trace.cpu().numpy() if hasattr(trace, "cpu") else np.asarray(trace)
+    rec = np.ascontiguousarray(raw).view(TRACE_DTYPE).reshape(raw.shape[0], -1)
+    return rec
+
+
+def bf16_bits_to_float(bits) -> np.ndarray:
+    return (np.asarray(bits, dtype=np.uint32) << 16).view(np.float32)

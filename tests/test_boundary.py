@@ -146,3 +146,24 @@ def test_unsupported_sizes():
                 obs_t=np.array([1], np.int32), obs_n=np.array([0], np.int32),
                 observed=np.zeros((1, 1, 1), np.int8))
     assert _create(prob)[0] == sa.SA_ERR_UNSUPPORTED
+
+
+def test_mlp_rejects_bad_params_before_touching_a_device():
+    lib = sa.lib()
+    h = C.c_void_p()
+    assert lib.sa_mlp_create(None, C.byref(h)) == sa.SA_ERR_ARG
+    bad = np.zeros(sa.MLP_N_PARAMS, dtype=np.float32)
+    bad[17] = np.nan
+    assert lib.sa_mlp_create(bad.ctypes.data, C.byref(h)) == sa.SA_ERR_DOMAIN
+    assert "not finite" in lib.sa_last_error().decode()
+    assert lib.sa_mlp_forward(None, None, 0, None, None) == sa.SA_ERR_ARG
+    assert lib.sa_mlp_destroy(None) == sa.SA_OK
+
+
+def test_mlp_param_packing_round_trip():
+    rng = np.random.default_rng(0)
+    W1, w2 = rng.normal(size=(32, 256)).astype(np.float32), rng.normal(size=256).astype(np.float32)
+    flat = sa.pack_mlp_params(W1, w2, 0.5)
+    assert flat.size == sa.MLP_N_PARAMS == 8449
+    p = sa.unpack_mlp_params(flat)
+    assert np.array_equal(p["W1"], W1) and np.array_equal(p["w2"], w2) and p["b2"] == 0.5

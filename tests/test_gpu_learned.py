@@ -1,0 +1,276 @@
+"""GPU parity of the learned proposal and of the step trace against the
+oracle's definitions (oracle/learned.py), through the C ABI.
+
+Exact where the arithmetic is exact: candidates, cost changes, accept flags,
+stage bests and winners, and the float32-defined features (their bf16 bit
+patterns).  The network's scores are float32 sums on the GPU and float64 in
+the oracle; the learned-run comparisons therefore use networks whose scores
+are exact dyadic numbers (few non-zero weights, multiples of 1/4 and 1/8),
+for which both sides build the same integer sampling table; general networks
+are covered piecewise (same features, the forward kernel's tile against the
+float64 reference in test_gpu_mlp.py)."""
+import numpy as np
+import pytest
+
+from oracle import learned
+from oracle import mlp_reference as M
+from paper_2506_19866_amd import synth
+from tests.problems import random_problem
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2506_19866_amd import sa
+    sa.lib()
+
+
+def _sa():
+    from paper_2506_19866_amd import sa
+    return sa
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.int8)).cuda()
+
+
+def _bf16_bits(f):
+    return (M.bf16(f).astype(np.float32).view(np.uint32) >> 16).astype(np.uint16)
+
+
+def _dyadic_model(seed, hidden_used=8):
+    """A network whose scores are exact in float32 and float64 alike and whose
+    table weights sit well away from integer boundaries."""
+    rng = np.random.default_rng(seed)
+    for attempt in range(200):
+        W1 = np.zeros((32, 256))
+        w2 = np.zeros(256)
+        for h in range(hidden_used):
+            W1[:7, h] = rng.integers(-4, 5, size=7) / 4
+            W1[31, h] = rng.integers(-2, 5) / 4
+            w2[h] = rng.integers(-8, 9) / 8
+        b2 = 0.125
+        # all scores this network can give: one-hot features only
+        lg = []
+        for co in range(3):
+            for cn in range(3):
+                for th in range(2):
+                    f = np.zeros(32)
+                    f[co] = 1
+                    f[3 + cn] = 1
+                    f[6] = th
+                    f[31] = 1
+                    lg.append(float(np.maximum(f @ W1, 0) @ w2 + b2))
+        d = np.array(lg)[:, None] - np.array(lg)[None, :]
+        w = np.exp(d[d <= 0]) * 65536
+        frac = w - np.floor(w)
+        if np.all((frac > 1e-3) & (frac < 1 - 1e-3) | (d[d <= 0] == 0)):
+            return {"W1": W1, "w2": w2, "b2": b2}
+        rng = np.random.default_rng(seed + 1000 * (attempt + 1))
+    raise RuntimeError("no dyadic model found")
+
+
+def _gpu_run(prob, x0, *, model=None, trace_every=0, trace_cap=0, **kw):
+    sa = _sa()
+    P = sa.Problem(prob)
+    net = sa.Mlp(sa.pack_mlp_params(model["W1"], model["w2"], model["b2"])) if model is not None else None
+    trace = None
+    if trace_every:
+        trace = torch.zeros((x0.shape[0], trace_cap * sa.TRACE_RECORD_BYTES), dtype=torch.uint8, device="cuda")
+    run = sa.Run(P, _dev(x0), model=net, trace=trace, trace_every=max(trace_every, 1), **kw)
+    x, cost, winner = run.best()
+    stats = run.stats()
+    rec = sa.decode_trace(trace) if trace is not None else None
+    run.close()
+    if net is not None:
+        net.close()
+    return {"x": x, "cost": cost, "winner": winner, "stats": stats, "trace": rec}
+
+
+def _compare_trace(gpu, ref, n_steps_per_chain):
+    rec = gpu["trace"]
+    seen = 0
+    for c, g, f, p, v, delta, flags in ref["trace"]:
+        r = rec[c, g]
+        assert (int(r["param"]), int(r["value"]), int(r["delta"]), int(r["flags"])) == (p, v, delta, flags), (c, g)
+        assert np.array_equal(r["features"], _bf16_bits(f)), (c, g, r["features"], _bf16_bits(f))
+        seen += 1
+    assert seen == rec.shape[0] * n_steps_per_chain
+
+
+def _problem(seed, N, E, C, T, K, O, noise=0.1, d=1, hard=1):
+    return random_problem(seed, n_nodes=N, n_edges=E, n_cond=C, n_steps=T, n_times=K, n_obs=O, noise=noise,
+                          clamps=(1, 2), step_size=d, hard=hard)[0]
+
+
+def _starts(prob, n, seed):
+    return synth.feasible_params(synth.rng_for(seed), n, prob["row_ptr"], prob["src"])
+
+
+# ---------------------------------------------------------------------------
+# trace of plain runs: the same chains as the plain kernel, plus features
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed,N,E,C,T,K,O,d,hard", [
+    (41, 12, 28, 4, 10, 3, 6, 1, 1),     # c1-like, one k-tile
+    (42, 20, 82, 8, 15, 4, 10, 1, 1),    # c2-like
+    (43, 70, 300, 20, 9, 4, 25, 2, 1),   # two k-tiles, two condition groups, d = 2
+    (44, 15, 40, 3, 8, 2, 5, 1, 0),      # penalty mode
+])
+def test_trace_of_plain_run_matches_oracle(seed, N, E, C, T, K, O, d, hard):
+    prob = _problem(seed, N, E, C, T, K, O, d=d, hard=hard)
+    n, S, L = 6, 2, 40
+    x0 = _starts(prob, n, seed + 1)
+    kw = dict(seed=900 + seed, T0=1.5, rho=0.5, n_stages=S, steps_per_stage=L)
+    ref = learned.run(prob, x0, model=None, refresh=16, eps=0.1, trace_every=1, **kw)
+    gpu = _gpu_run(prob, x0, trace_every=1, trace_cap=S * L, refresh_every=16, **kw)
+    assert gpu["stats"]["best_cost"].tolist() == ref["stage_best"]
+    assert gpu["stats"]["winner"].tolist() == ref["stage_winner"]
+    _compare_trace(gpu, ref, S * L)
+    # the traced kernel runs the same chains as the plain kernel
+    sa = _sa()
+    run = sa.Run(sa.Problem(prob), _dev(x0), **kw)
+    assert run.stats()["best_cost"].tolist() == ref["stage_best"]
+    run.close()
+
+
+def test_trace_every_and_capacity():
+    prob = _problem(45, 12, 30, 3, 8, 3, 5)
+    n, S, L = 4, 3, 30
+    x0 = _starts(prob, n, 7)
+    kw = dict(seed=5, T0=1.0, rho=0.7, n_stages=S, steps_per_stage=L, first_stage=1)
+    ref = learned.run(prob, x0, model=None, refresh=8, eps=0.0, trace_every=7, **kw)
+    # steps g = 30 .. 119 that are multiples of 7: 35, 42, ..., 119 -> 13; capacity 10 keeps the first 10
+    gpu = _gpu_run(prob, x0, trace_every=7, trace_cap=10, refresh_every=8, **kw)
+    rec = gpu["trace"]
+    first = [t for t in ref["trace"]]
+    assert len(first) == n * 13
+    for c, g, f, p, v, delta, flags in first:
+        slot = (g - 35) // 7
+        if slot >= 10:
+            continue
+        r = rec[c, slot]
+        assert (int(r["param"]), int(r["value"]), int(r["delta"]), int(r["flags"])) == (p, v, delta, flags)
+        assert np.array_equal(r["features"], _bf16_bits(f))
+
+
+# ---------------------------------------------------------------------------
+# learned runs with exactly scored networks: bit-exact against the oracle
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed,N,E,C,T,K,O,d,eps,R", [
+    (51, 12, 28, 4, 10, 3, 6, 1, 0.1, 16),
+    (52, 20, 82, 8, 15, 4, 10, 1, 0.0, 8),
+    (53, 40, 160, 5, 7, 2, 12, 2, 0.3, 5),
+])
+def test_learned_run_matches_oracle(seed, N, E, C, T, K, O, d, eps, R):
+    prob = _problem(seed, N, E, C, T, K, O, d=d)
+    n, S, L = 5, 2, 48
+    x0 = _starts(prob, n, seed + 2)
+    model = _dyadic_model(seed)
+    kw = dict(seed=700 + seed, T0=1.2, rho=0.6, n_stages=S, steps_per_stage=L)
+    ref = learned.run(prob, x0, model=model, refresh=R, eps=eps, trace_every=1, **kw)
+    gpu = _gpu_run(prob, x0, model=model, trace_every=1, trace_cap=S * L, refresh_every=R, eps_plain=eps, **kw)
+    sources = [s for _, _, s, *_ in ref["steps"]]
+    assert sources.count(learned.SOURCE_LEARNED) > 0.3 * len(sources)
+    _compare_trace(gpu, ref, S * L)
+    assert gpu["stats"]["best_cost"].tolist() == ref["stage_best"]
+    assert gpu["stats"]["winner"].tolist() == ref["stage_winner"]
+    assert np.array_equal(gpu["x"], ref["x"]) and gpu["cost"] == ref["cost"]
+
+
+def test_learned_run_without_trace_and_always_plain():
+    """Without a trace the learned kernel gives the same run; with eps = 1 it
+    is the plain method."""
+    prob = _problem(54, 16, 50, 4, 10, 3, 6)
+    n, S, L = 8, 3, 40
+    x0 = _starts(prob, n, 3)
+    model = _dyadic_model(54)
+    kw = dict(seed=31, T0=1.0, rho=0.5, n_stages=S, steps_per_stage=L)
+    ref = learned.run(prob, x0, model=model, refresh=10, eps=0.2, **kw)
+    gpu = _gpu_run(prob, x0, model=model, refresh_every=10, eps_plain=0.2, **kw)
+    assert gpu["stats"]["best_cost"].tolist() == ref["stage_best"]
+    assert np.array_equal(gpu["x"], ref["x"])
+    plain = _gpu_run(prob, x0, **kw)
+    always = _gpu_run(prob, x0, model=model, refresh_every=10, eps_plain=1.0, **kw)
+    assert always["stats"]["best_cost"].tolist() == plain["stats"]["best_cost"].tolist()
+    assert np.array_equal(always["x"], plain["x"])
+
+
+def test_c3_learned_stage_sampled_chains():
+    """The Mtb-scale workload at the launch configuration of the learned
+    benchmark (16384 chains, 500 steps per stage, refresh 16): chains sampled
+    from the first stage against the oracle's serial learned chain."""
+    sa = _sa()
+    prob = synth.load_workload("c3")
+    sched = synth.bench_schedule("c3")
+    n, L = sched["n_chains"], sched["steps_per_stage"]
+    x0 = synth.start_vectors("c3", prob, n)
+    model = _dyadic_model(55)
+    P = sa.Problem(prob)
+    net = sa.Mlp(sa.pack_mlp_params(model["W1"], model["w2"], model["b2"]))
+    run = sa.Run(P, _dev(x0), seed=sched["seed"], T0=sched["T0"], rho=sched["rho"], n_stages=1,
+                 steps_per_stage=L, model=net, refresh_every=16, eps_plain=0.1)
+    cost, xb = run.chain_best()
+    run.close()
+    net.close()
+    for c in (0, n - 1):
+        ref = learned.run(prob, x0[c:c + 1], seed=sched["seed"], T0=sched["T0"], rho=sched["rho"], n_stages=1,
+                          steps_per_stage=L, model=model, refresh=16, eps=0.1, first_chain=c)
+        assert ref["stage_best"][0] == cost[c]
+        assert np.array_equal(ref["x"], xb[c])
+
+
+# ---------------------------------------------------------------------------
+# argument checks of the learned path
+# ---------------------------------------------------------------------------
+def test_learned_run_rejections():
+    sa = _sa()
+    prob = _problem(56, 12, 28, 2, 6, 2, 4)
+    x0 = _dev(_starts(prob, 2, 1))
+    P = sa.Problem(prob)
+    model = _dyadic_model(56)
+    net = sa.Mlp(sa.pack_mlp_params(model["W1"], model["w2"], model["b2"]))
+    kw = dict(seed=1, T0=1.0, rho=0.9, n_stages=1, steps_per_stage=4, launch=False)
+    with pytest.raises(sa.SAError) as e:
+        sa.Run(P, x0, model=net, refresh_every=0, **kw)
+    assert e.value.code == sa.SA_ERR_ARG
+    with pytest.raises(sa.SAError) as e:
+        sa.Run(P, x0, model=net, eps_plain=1.5, **kw)
+    assert e.value.code == sa.SA_ERR_ARG
+    with pytest.raises(sa.SAError) as e:
+        sa.Run([P, P], [x0, x0], model=net, **kw)
+    assert e.value.code == sa.SA_ERR_UNSUPPORTED
+    big_prob = _problem(57, 130, 400, 2, 5, 2, 10)
+    with pytest.raises(sa.SAError) as e:
+        sa.Run(sa.Problem(big_prob), _dev(_starts(big_prob, 2, 1)), model=net, **kw)
+    assert e.value.code == sa.SA_ERR_UNSUPPORTED
+    net.close()
+
+
+def test_collect_and_train_pipeline():
+    """Trace rows decoded on the device match the records; labels mark the
+    accepted improving moves; a few training steps lower the loss."""
+    sa = _sa()
+    from paper_2506_19866_amd import proposal
+    prob = _problem(58, 20, 82, 8, 15, 4, 10)
+    n, S, L = 64, 4, 100
+    x0 = _starts(prob, n, 9)
+    X, y, stats = proposal.collect(sa.Problem(prob), _dev(x0), seed=3, T0=1.0, rho=0.6, n_stages=S,
+                                   steps_per_stage=L, trace_every=3)
+    rows_per_chain = len(range(0, S * L, 3))
+    assert X.shape == (n * rows_per_chain, 32)
+    ref = learned.run(prob, x0[:2], seed=3, T0=1.0, rho=0.6, n_stages=1, steps_per_stage=L, model=None,
+                      refresh=16, eps=0.1, trace_every=3)
+    Xc = X.float().cpu().numpy().reshape(n, rows_per_chain, 32)
+    yc = y.cpu().numpy().reshape(n, rows_per_chain)
+    for c, g, f, p, v, delta, flags in ref["trace"]:
+        assert np.array_equal(Xc[c, g // 3], M.bf16(f).astype(np.float32))
+        assert yc[c, g // 3] == float((flags & 1) and delta < 0)
+    net = sa.Mlp(proposal.init_params(1))
+    losses = proposal.train(net, X, y, epochs=3, batch=512, lr=3e-3, seed=0)
+    assert losses[-1] < losses[0]
+    net.close()
