@@ -66,10 +66,11 @@ struct sa_run {
   bool persistent = false;       // many-network kernel (else the specialised one)
   int waves = 4;                 // chains per work item (persistent kernel)
   int cus = 256;
-  int blocks_per_cu = 1;
+  std::vector<int> blocks_per_cu;  // per launch group
   std::vector<int64_t> x_off, w_off;
-  std::vector<int> item_class_begin, item_class_count, item_class_d;  // per step-size class
-  size_t smem = 0;
+  // launch groups of the persistent kernel: (size class, step size)
+  std::vector<int> item_class_begin, item_class_count, item_class_d, item_class_cls;
+  std::vector<size_t> class_smem;
   int8_t *x0 = nullptr, *xbest = nullptr, *xwin = nullptr;
   int32_t *cbest = nullptr;
   uint32_t *cstats = nullptr, *tau = nullptr, *queue = nullptr;
@@ -461,7 +462,8 @@ static void free_run(sa_run *r) {
 }
 
 // Work items of the persistent kernel: (network, first chain) with `waves`
-// chains each, grouped by step size, longest networks first (per-step work
+// chains each, in launch groups of one size class and one step size (largest
+// class first), longest networks first within a group (per-step work
 // ~ C * T_s * m-tiles * k-tiles).  Returns the item count.
 static int build_items(sa_run *r, int waves, std::vector<int32_t> &net, std::vector<int32_t> &chain0) {
   net.clear();
@@ -469,26 +471,37 @@ static int build_items(sa_run *r, int waves, std::vector<int32_t> &net, std::vec
   r->item_class_begin.clear();
   r->item_class_count.clear();
   r->item_class_d.clear();
+  r->item_class_cls.clear();
+  r->class_smem.clear();
   const int np = (int)r->probs.size();
-  for (int d = 1; d <= 2; ++d) {
-    std::vector<int> order;
-    for (int i = 0; i < np; ++i)
-      if (r->probs[i]->dev.d == d) order.push_back(i);
-    if (order.empty()) continue;
-    auto work = [&](int i) {
-      const sa::DevProblem &p = r->probs[i]->dev;
-      return (long long)p.C * p.T * p.nm * p.nk;
-    };
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
-    r->item_class_begin.push_back((int)net.size());
-    r->item_class_d.push_back(d);
-    for (int i : order)
-      for (int64_t c = 0; c < r->n; c += waves) {
-        net.push_back(i);
-        chain0.push_back((int32_t)c);
+  for (int cls = sa::kPersistentClasses - 1; cls >= 0; --cls)
+    for (int d = 1; d <= 2; ++d) {
+      std::vector<int> order;
+      size_t smem = 0;
+      for (int i = 0; i < np; ++i) {
+        const sa::DevProblem &p = r->probs[i]->dev;
+        if (p.d == d && sa::persistent_class(p.nm) == cls) {
+          order.push_back(i);
+          smem = std::max(smem, sa::persistent_smem_bytes(p, waves));
+        }
       }
-    r->item_class_count.push_back((int)net.size() - r->item_class_begin.back());
-  }
+      if (order.empty()) continue;
+      auto work = [&](int i) {
+        const sa::DevProblem &p = r->probs[i]->dev;
+        return (long long)p.C * p.T * p.nm * p.nk;
+      };
+      std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
+      r->item_class_begin.push_back((int)net.size());
+      r->item_class_d.push_back(d);
+      r->item_class_cls.push_back(cls);
+      r->class_smem.push_back(smem);
+      for (int i : order)
+        for (int64_t c = 0; c < r->n; c += waves) {
+          net.push_back(i);
+          chain0.push_back((int32_t)c);
+        }
+      r->item_class_count.push_back((int)net.size() - r->item_class_begin.back());
+    }
   return (int)net.size();
 }
 
@@ -497,11 +510,10 @@ static int upload_items(sa_run *r, int waves) {
   build_items(r, waves, net, chain0);
   SA_HIP(hipMemcpy(r->item_net, net.data(), net.size() * 4, hipMemcpyHostToDevice), "copy items");
   SA_HIP(hipMemcpy(r->item_chain0, chain0.data(), chain0.size() * 4, hipMemcpyHostToDevice), "copy items");
-  size_t smem = 0;
-  for (sa_problem *p : r->probs) smem = std::max(smem, sa::persistent_smem_bytes(p->dev, waves));
-  r->smem = smem;
   r->waves = waves;
-  r->blocks_per_cu = sa::persistent_blocks_per_cu(waves, smem);
+  r->blocks_per_cu.clear();
+  for (size_t k = 0; k < r->item_class_cls.size(); ++k)
+    r->blocks_per_cu.push_back(sa::persistent_blocks_per_cu(r->item_class_cls[k], waves, r->class_smem[k]));
   return SA_OK;
 }
 
@@ -556,8 +568,10 @@ static int enqueue_stage(sa_run *r, int32_t st, hipStream_t stream) {
       a.xbest = r->xbest;
       a.cbest = r->cbest;
       a.cstats = r->cstats;
-      const int grid = std::max(1, std::min(a.n_items, r->cus * r->blocks_per_cu));
-      SA_HIP((hipError_t)sa::launch_persistent(a, r->item_class_d[k], grid, r->smem, stream), "persistent launch");
+      const int grid = std::max(1, std::min(a.n_items, r->cus * r->blocks_per_cu[k]));
+      SA_HIP((hipError_t)sa::launch_persistent(a, r->item_class_cls[k], r->item_class_d[k], grid, r->class_smem[k],
+                                               stream),
+             "persistent launch");
     }
   }
   if (timed) SA_HIP(hipEventRecord(r->ev_stop[st], stream), "event record");
@@ -589,7 +603,7 @@ static int autotune_waves(sa_run *r, hipStream_t s) {
   int rc = SA_OK;
   for (int w : candidates) {
     if ((rc = upload_items(r, w)) != SA_OK) break;
-    hipError_t e = hipMemsetAsync(r->queue, 0, 2 * sizeof(uint32_t), s);
+    hipError_t e = hipMemsetAsync(r->queue, 0, sa::kPersistentQueues * sizeof(uint32_t), s);
     if (e == hipSuccess) e = hipEventRecord(e0, s);
     if (e != hipSuccess) {
       rc = hip_fail(e, "autotune");
@@ -614,7 +628,7 @@ static int autotune_waves(sa_run *r, hipStream_t s) {
   if (rc != SA_OK) return rc;
   rc = upload_items(r, best);
   if (rc != SA_OK) return rc;
-  SA_HIP(hipMemsetAsync(r->queue, 0, 2 * sizeof(uint32_t), s), "queue reset");
+  SA_HIP(hipMemsetAsync(r->queue, 0, sa::kPersistentQueues * sizeof(uint32_t), s), "queue reset");
   return SA_OK;
 }
 
@@ -762,7 +776,7 @@ extern "C" int sa_run_create(sa_problem *const *probs, int32_t n_probs, const sa
   alloc((void **)&r->cbest, (size_t)(n * n_probs) * 4);
   alloc((void **)&r->cstats, (size_t)(n * n_probs) * 16);
   alloc((void **)&r->tau, all_tau.size() * 4);
-  alloc((void **)&r->queue, 2 * sizeof(uint32_t));
+  alloc((void **)&r->queue, sa::kPersistentQueues * sizeof(uint32_t));
   alloc((void **)&r->rec, (size_t)std::max(S, 1) * n_probs * sizeof(sa::StageRecord));
   alloc((void **)&r->probs_dev, (size_t)n_probs * sizeof(sa::DevProblem));
   alloc((void **)&r->x_off_dev, (size_t)n_probs * 8);
@@ -784,7 +798,7 @@ extern "C" int sa_run_create(sa_problem *const *probs, int32_t n_probs, const sa
   if (e == hipSuccess) e = hipMemcpyAsync(r->probs_dev, dps.data(), dps.size() * sizeof(sa::DevProblem), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(r->x_off_dev, r->x_off.data(), (size_t)n_probs * 8, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(r->w_off_dev, r->w_off.data(), (size_t)n_probs * 8, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemsetAsync(r->queue, 0, 2 * sizeof(uint32_t), s);
+  if (e == hipSuccess) e = hipMemsetAsync(r->queue, 0, sa::kPersistentQueues * sizeof(uint32_t), s);
   // lambda >= 1, so V(x0) = 0 exactly when the cost with lambda equals the
   // cost with lambda = 0 (the mismatch alone)
   for (int i = 0; i < n_probs && e == hipSuccess; ++i) {
@@ -822,7 +836,8 @@ extern "C" int sa_run_create(sa_problem *const *probs, int32_t n_probs, const sa
       rc = upload_items(r, desc->chains_per_block ? desc->chains_per_block : 4);
     if (rc == SA_OK) {
       const size_t lds_max = 160 * 1024;
-      if (r->smem > lds_max) rc = fail(SA_ERR_UNSUPPORTED, "many-network kernel needs %zu bytes of LDS", r->smem);
+      for (size_t smem : r->class_smem)
+        if (smem > lds_max) rc = fail(SA_ERR_UNSUPPORTED, "many-network kernel needs %zu bytes of LDS", smem);
     }
     if (rc != SA_OK) {
       free_run(r);

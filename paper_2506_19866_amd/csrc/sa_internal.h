@@ -120,7 +120,7 @@ struct BatchReduceArgs {
   const uint32_t *cstats;
   int8_t *xwin;
   StageRecord *rec;           // [n_probs] of this stage
-  uint32_t *queue;            // [2] work counters to reset, or null
+  uint32_t *queue;            // [kPersistentQueues] work counters to reset, or null
 };
 
 // One traced annealing step (the C ABI's sa_trace_record).
@@ -150,12 +150,16 @@ int launch_simulate(const DevProblem &pb, const int8_t *x, int64_t n, int8_t *tr
 int launch_stage(const DevProblem &pb, const StageArgs &sa, void *stream);
 size_t stage_smem_bytes(const DevProblem &pb, int waves_per_block);
 int stage_waves_per_block(const DevProblem &pb);
-int launch_persistent(const BatchArgs &a, int d, int grid, size_t smem, void *stream);
+// Persistent launch of size class cls (layout (4,1), (8,2) or (10,3)) and step size d.
+int launch_persistent(const BatchArgs &a, int cls, int d, int grid, size_t smem, void *stream);
+int persistent_class(int nm);
 int launch_batch_reduce(const BatchReduceArgs &ra, void *stream);
 size_t persistent_smem_bytes(const DevProblem &pb, int waves);
-// Workgroups of `waves` waves with `smem` bytes of LDS that fit on one CU.
-int persistent_blocks_per_cu(int waves, size_t smem);
+// Workgroups of `waves` waves with `smem` bytes of LDS of class cls that fit on one CU.
+int persistent_blocks_per_cu(int cls, int waves, size_t smem);
 constexpr int kPersistentTilesM = 10, kPersistentTilesK = 3;  // networks up to 159 nodes
+constexpr int kPersistentClasses = 3;
+constexpr int kPersistentQueues = 2 * kPersistentClasses;     // one work counter per (class, step size)
 int launch_learned_stage(const DevProblem &pb, const StageArgs &sa, const LearnedArgs &la, void *stream);
 // LDS of a learned-stage workgroup; prepare sets the kernel's LDS limit to it.
 size_t learned_smem_bytes(const DevProblem &pb, bool model);

@@ -1,14 +1,14 @@
-// sa_k_persist.hip -- many networks of uneven size in one persistent launch
+// sa_k_persist.hip -- many networks of uneven size in persistent launches
 // per temperature stage (Table 1 for every network), and the per-network
-// stage reduction.  Every network runs in the largest register layout with
-// its own tile counts as runtime bounds, so one kernel serves all sizes.
+// stage reduction.  Networks are grouped into size classes; a class runs in
+// its largest register layout with each network's own tile counts as runtime
+// bounds, so small networks keep small register footprints (and high
+// occupancy) while one kernel serves every size within a class.
 #include "sa_chain.h"
 
 namespace sa {
 
-constexpr int kNMx = kPersistentTilesM, kNKx = kPersistentTilesK;
-
-template <int D>
+template <int MX, int KX, int D>
 __global__ __launch_bounds__(512) void persistent_kernel(BatchArgs a) {
   extern __shared__ uint32_t smem[];
   __shared__ int s_item;
@@ -45,7 +45,7 @@ __global__ __launch_bounds__(512) void persistent_kernel(BatchArgs a) {
       job.dcap = a.dcap;
       job.tau = a.tau;
       uint8_t *lds = reinterpret_cast<uint8_t *>(smem + 2 * n_obs) + (size_t)wv * chain_lds_bytes(pb);
-      run_chain<kNMx, kNKx, D, true>(pb, job, lane, lds, lds_r, lds_w);
+      run_chain<MX, KX, D, true>(pb, job, lane, lds, lds_r, lds_w);
     }
     __syncthreads();  // the block's LDS is reused by the next item
   }
@@ -92,10 +92,8 @@ __global__ __launch_bounds__(256) void batch_reduce_kernel(BatchReduceArgs ra) {
     r->uphill = sums[1][0];
     r->neutral = sums[2][0];
     r->infeasible = sums[3][0];
-    if (net == 0 && ra.queue) {  // one queue per step-size class
-      ra.queue[0] = 0u;
-      ra.queue[1] = 0u;
-    }
+    if (net == 0 && ra.queue)  // one work counter per (size class, step size) launch
+      for (int q = 0; q < kPersistentQueues; ++q) ra.queue[q] = 0u;
   }
   const int P = ra.probs[net].P;
   const int8_t *from = ra.xbest + ra.x_off[net] + winner * P;
@@ -107,18 +105,43 @@ size_t persistent_smem_bytes(const DevProblem &pb, int waves) {
   return (size_t)2 * obs_dwords(pb) * 4 + (size_t)waves * chain_lds_bytes(pb);
 }
 
-int persistent_blocks_per_cu(int waves, size_t smem) {
+// size classes: (m-tiles, k-tiles) of the layout each class runs in
+#define SA_PERSISTENT_CLASSES(X) X(0, 4, 1) X(1, 8, 2) X(2, 10, 3)
+
+int persistent_class(int nm) { return nm <= 4 ? 0 : nm <= 8 ? 1 : 2; }
+
+int persistent_blocks_per_cu(int cls, int waves, size_t smem) {
   int blocks = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, persistent_kernel<1>, 64 * waves, smem) != hipSuccess)
-    return 1;
+  hipError_t e = hipErrorInvalidValue;
+#define SA_CASE(C, M, K) \
+  case C:                \
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, persistent_kernel<M, K, 1>, 64 * waves, smem); \
+    break;
+  switch (cls) {
+    SA_PERSISTENT_CLASSES(SA_CASE)
+    default:
+      break;
+  }
+#undef SA_CASE
+  if (e != hipSuccess) return 1;
   return blocks > 0 ? blocks : 1;
 }
 
-int launch_persistent(const BatchArgs &a, int d, int grid, size_t smem, void *stream) {
-  if (d == 1)
-    persistent_kernel<1><<<grid, 64 * a.waves, smem, (hipStream_t)stream>>>(a);
-  else
-    persistent_kernel<2><<<grid, 64 * a.waves, smem, (hipStream_t)stream>>>(a);
+int launch_persistent(const BatchArgs &a, int cls, int d, int grid, size_t smem, void *stream) {
+  hipStream_t s = (hipStream_t)stream;
+#define SA_CASE(C, M, K)                                                    \
+  case C:                                                                   \
+    if (d == 1)                                                             \
+      persistent_kernel<M, K, 1><<<grid, 64 * a.waves, smem, s>>>(a);       \
+    else                                                                    \
+      persistent_kernel<M, K, 2><<<grid, 64 * a.waves, smem, s>>>(a);       \
+    break;
+  switch (cls) {
+    SA_PERSISTENT_CLASSES(SA_CASE)
+    default:
+      return (int)hipErrorInvalidValue;
+  }
+#undef SA_CASE
   return (int)hipGetLastError();
 }
 
