@@ -232,6 +232,36 @@ def bench_learned(args) -> int:
     return 0
 
 
+def bench_learned_cost(args) -> int:
+    """Per-stage cost of the learned kernel on c3 against the plain stage
+    kernel: the learned kernel without a network (refreshing the per-node
+    aggregates only) and with a network at several refresh intervals.  The
+    network's weights do not change the work; a freshly initialised one is
+    used.  One JSON line per configuration, mean stage-kernel ms over the
+    stages after the first."""
+    import torch
+    from paper_2506_19866_amd import proposal, sa, synth
+    prob, s = synth.load_workload("c3"), synth.bench_schedule("c3")
+    n, L = s["n_chains"], s["steps_per_stage"]
+    x0 = torch.from_numpy(synth.start_vectors("c3", prob, n)).cuda()
+    P = sa.Problem(prob)
+    net = sa.Mlp(proposal.init_params(args.model_seed))
+    trace = torch.zeros((n, sa.TRACE_RECORD_BYTES), dtype=torch.uint8, device="cuda")
+    configs = [("plain", {})]
+    for R in args.refresh_list:
+        configs.append((f"aggregates only, refresh {R}", dict(trace=trace, trace_every=1 << 30, refresh_every=R)))
+        configs.append((f"learned, refresh {R}", dict(model=net, refresh_every=R, eps_plain=args.eps)))
+    for label, kw in configs:
+        run = sa.Run(P, x0, seed=s["seed"], T0=s["T0"], rho=s["rho"], n_stages=args.steps, steps_per_stage=L,
+                     record_times=True, **kw)
+        ms = run.stage_times_ms()
+        run.close()
+        print(json.dumps({"config": label, "stage_ms": float(np.mean(ms[1:] if len(ms) > 1 else ms)),
+                          "stages": args.steps}), flush=True)
+    net.close()
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -241,8 +271,10 @@ def main() -> int:
                     help="c4 = the batched workload (256 uneven networks, one persistent launch per stage)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--mode", default="throughput", choices=["throughput", "learned"],
-                    help="learned: train the proposal network on c2 traces and compare time-to-target on c3")
+    ap.add_argument("--mode", default="throughput", choices=["throughput", "learned", "learned-cost"],
+                    help="learned: train the proposal network on c2 traces and compare time-to-target on c3; "
+                         "learned-cost: per-stage cost of the learned kernel against the plain one on c3")
+    ap.add_argument("--refresh-list", type=int, nargs="+", default=[16, 64, 256])
     ap.add_argument("--trace-rows", type=int, default=1 << 20)
     ap.add_argument("--epochs", type=int, default=4)
     ap.add_argument("--lr", type=float, default=1e-3)
@@ -273,6 +305,8 @@ def main() -> int:
     from paper_2506_19866_amd import sa, synth
     if args.mode == "learned":
         return bench_learned(args)
+    if args.mode == "learned-cost":
+        return bench_learned_cost(args)
 
     name = args.workload
     if name == "c4":
