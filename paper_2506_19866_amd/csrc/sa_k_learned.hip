@@ -63,6 +63,7 @@ __global__ __launch_bounds__(256) void learned_stage_kernel(DevProblem pb, Stage
   hk.msh = reinterpret_cast<float *>(hk.tbl + learned_tbl_words(pb));
   hk.eh = hk.msh + round4(pb.N);
   hk.ah = hk.eh + round4(pb.N);
+  hk.fst = reinterpret_cast<uint4 *>(hk.ah + round4(pb.N));
   hk.b2 = model ? *la.b2 : 0.f;
   hk.mn = 0.f;
   hk.total = 0u;

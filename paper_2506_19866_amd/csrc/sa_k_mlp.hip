@@ -92,7 +92,7 @@ __global__ __launch_bounds__(256) void mlp_train_kernel(MlpTrainArgs a) {
       for (int hf = 0; hf < 2; ++hf) {
         const v4f z = mfma_bf16(as_v8bf(xa[hf]), w, zero);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) part[hf][i] += bf16_round(fmaxf(z[i], 0.f)) * w2c[ht];
+        for (int i = 0; i < 4; ++i) part[hf][i] += bf16_round(relu(z[i])) * w2c[ht];
       }
     }
 #pragma unroll
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(256) void mlp_train_kernel(MlpTrainArgs a) {
       float s = 0.f;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        s += bf16_round(fmaxf(z0[i], 0.f)) * dl[0][i] + bf16_round(fmaxf(z1[i], 0.f)) * dl[1][i];
+        s += bf16_round(relu(z0[i])) * dl[0][i] + bf16_round(relu(z1[i])) * dl[1][i];
         dz[i] = (__bf16)(z0[i] > 0.f ? dl[0][i] * w2c[ht] : 0.f);
         dz[4 + i] = (__bf16)(z1[i] > 0.f ? dl[1][i] * w2c[ht] : 0.f);
       }

@@ -35,10 +35,13 @@ namespace sa {
 __host__ __device__ inline int learned_tbl_words(const DevProblem &pb) {
   return 2 * pb.P > 3 * 64 * pb.nk ? 2 * pb.P : 3 * 64 * pb.nk;
 }
+// Feature rows of 32 moves staged between their computation and the tiles.
+constexpr int kStageMoves = 32;
 // LDS of one chain: the plain chain area, the vector at the last refresh
-// [P4], the table, and three float node features [N4] each.
+// [P4], the table, three float node features [N4] each, and the staged
+// feature rows (32 x 64 bytes).
 __host__ __device__ inline int learned_wave_bytes(const DevProblem &pb) {
-  return chain_lds_bytes(pb) + round4(pb.P) + 4 * learned_tbl_words(pb) + 12 * round4(pb.N);
+  return chain_lds_bytes(pb) + round4(pb.P) + 4 * learned_tbl_words(pb) + 12 * round4(pb.N) + 64 * kStageMoves;
 }
 
 // bytewise w * v for bytes w <= 3, v <= 2 (products <= 6: no carries)
@@ -158,11 +161,17 @@ struct NodeFeatures {
   float lt, mn;
 };
 
-// Features 8*grp .. 8*grp+7 of the move p: old -> v (grp = 0..3), and
-// whether the move raises V.
-__device__ __forceinline__ v8bf move_features(int grp, int p, int old, int v, const uint32_t *pinfo,
-                                              const NodeFeatures &nf, const uint8_t *outnz, const uint8_t *inplus,
-                                              bool &raises) {
+__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
+  typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+  const v2bf t = {(__bf16)lo, (__bf16)hi};
+  return __builtin_bit_cast(uint32_t, t);
+}
+
+// The 32 features of the move p: old -> v as bf16 pairs (feature 2q in the
+// low half of word q), and whether the move raises V.
+__device__ __forceinline__ void move_feature_words(int p, int old, int v, const uint32_t *pinfo, const NodeFeatures &nf,
+                                                   const uint8_t *outnz, const uint8_t *inplus, bool &raises,
+                                                   uint4 (&out)[4]) {
   const uint32_t info = pinfo[p];
   const int i = (int)(info & 127u), j = (int)((info >> 7) & 127u);
   const int indeg = (int)((info >> 14) & 127u), outdeg = (int)((info >> 21) & 127u);
@@ -176,18 +185,15 @@ __device__ __forceinline__ v8bf move_features(int grp, int p, int old, int v, co
   const int on_j = outnz[j], ip_i = inplus[i];
   const int on_new = on_j + (v != 0) - (old != 0), ip_new = ip_i + (v == 1) - (old == 1);
   raises = edge && ((on_new == 0 && on_j > 0) || (ip_new == 0 && ip_i > 0));
-  const float g0[8] = {co == 0 ? 1.f : 0.f, co == 1 ? 1.f : 0.f, co == 2 ? 1.f : 0.f, cn == 0 ? 1.f : 0.f,
-                       cn == 1 ? 1.f : 0.f, cn == 2 ? 1.f : 0.f, edge ? 0.f : 1.f, e};
-  const float g1[8] = {obs_i ? 1.f : 0.f, eh_i, ah_i, msh_j, msh_i, f13, f14, obs_j ? 1.f : 0.f};
-  const float g2[8] = {eh_j, (float)indeg / 8.f, (float)outdeg / 8.f, nf.lt, nf.mn, raises ? 1.f : 0.f,
-                       (float)ip_i / 8.f, edge ? (float)on_j / 8.f : 0.f};
-  v8bf out;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const float g3 = k == 7 ? 1.f : 0.f;
-    out[k] = (__bf16)(grp == 0 ? g0[k] : grp == 1 ? g1[k] : grp == 2 ? g2[k] : g3);
-  }
-  return out;
+  out[0] = make_uint4(pack_bf16x2(co == 0 ? 1.f : 0.f, co == 1 ? 1.f : 0.f),
+                      pack_bf16x2(co == 2 ? 1.f : 0.f, cn == 0 ? 1.f : 0.f),
+                      pack_bf16x2(cn == 1 ? 1.f : 0.f, cn == 2 ? 1.f : 0.f), pack_bf16x2(edge ? 0.f : 1.f, e));
+  out[1] = make_uint4(pack_bf16x2(obs_i ? 1.f : 0.f, eh_i), pack_bf16x2(ah_i, msh_j), pack_bf16x2(msh_i, f13),
+                      pack_bf16x2(f14, obs_j ? 1.f : 0.f));
+  out[2] = make_uint4(pack_bf16x2(eh_j, (float)indeg / 8.f), pack_bf16x2((float)outdeg / 8.f, nf.lt),
+                      pack_bf16x2(nf.mn, raises ? 1.f : 0.f),
+                      pack_bf16x2((float)ip_i / 8.f, edge ? (float)on_j / 8.f : 0.f));
+  out[3] = make_uint4(0u, 0u, 0u, pack_bf16x2(0.f, 1.f));
 }
 
 __device__ __forceinline__ float wave_max_f(float v) {
@@ -206,6 +212,7 @@ struct LearnedHooks {
   uint8_t *xref;             // vector at the last refresh
   uint32_t *tbl;             // cumulative weights (or aggregates during a refresh)
   float *msh, *eh, *ah;
+  uint4 *fst;                // staged feature rows [kStageMoves][4]
   float b2, mn;
   uint32_t total;
   TraceRecord *trace;        // this chain's records, or null
@@ -226,21 +233,35 @@ struct LearnedHooks {
       reinterpret_cast<uint32_t *>(xref)[i] = reinterpret_cast<const uint32_t *>(xcur)[i];
     const int g = lane >> 4, r = lane & 15;
     const NodeFeatures nf = nodes();
-    // scores of all moves, 16 per tile; masked moves score -inf
-    for (int m0 = 0; m0 < M2; m0 += 16) {
-      const int mm = m0 + r;
-      const bool valid = mm < M2;
-      const int p = valid ? mm >> 1 : 0;
-      const int old = (int)(int8_t)xcur[p];
-      const bool edge = p < E;
-      const int cn = ((edge ? old + 1 : old) + 1 + (mm & 1)) % 3;
-      const int v = edge ? cn - 1 : cn;
-      bool raises;
-      const v8bf f = move_features(g, p, old, v, pinfo, nf, outnz, inplus, raises);
-      const float l = mlp_tile_logit(f, w1f, w2f, lane, b2);
-      if (g == 0 && valid) tbl[mm] = __float_as_uint((pb->hard && raises) ? -INFINITY : l);
+    // scores of all moves; masked moves score -inf.  Lanes 0-31 compute the
+    // feature rows of 32 moves once, the two tiles read them back as MFMA
+    // operands; lane 16t + r holds move r of tile t, so it also stores that
+    // move's score.
+    for (int m0 = 0; m0 < M2; m0 += kStageMoves) {
+      const int mm = m0 + lane;
+      bool raises = false;
+      if (lane < kStageMoves) {
+        uint4 w[4] = {make_uint4(0u, 0u, 0u, 0u), make_uint4(0u, 0u, 0u, 0u), make_uint4(0u, 0u, 0u, 0u),
+                      make_uint4(0u, 0u, 0u, 0u)};
+        if (mm < M2) {
+          const int p = mm >> 1;
+          const int old = (int)(int8_t)xcur[p];
+          const bool edge = p < E;
+          const int cn = ((edge ? old + 1 : old) + 1 + (mm & 1)) % 3;
+          move_feature_words(p, old, edge ? cn - 1 : cn, pinfo, nf, outnz, inplus, raises, w);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) fst[lane * 4 + q] = w[q];
+      }
+      wave_sync();
+#pragma unroll
+      for (int t = 0; t < kStageMoves / 16; ++t) {
+        if (m0 + 16 * t >= M2) break;
+        const float l = mlp_tile_logit(as_v8bf(fst[(16 * t + r) * 4 + g]), w1f, w2f, lane, b2);
+        if (g == t && mm < M2) tbl[mm] = __float_as_uint((pb->hard && raises) ? -INFINITY : l);
+      }
+      wave_sync();
     }
-    wave_sync();
     // integer weights and their inclusive prefix sums, one contiguous chunk per lane
     float lmax = -INFINITY;
     for (int i = lane; i < M2; i += kWave) lmax = fmaxf(lmax, __uint_as_float(tbl[i]));
@@ -316,12 +337,12 @@ struct LearnedHooks {
     const int64_t slot = rel / la.trace_every;
     if (slot >= la.trace_cap) return;
     TraceRecord *rec = trace + slot;
-    if (lane < 4) {
-      bool raises;
-      const v8bf f = move_features(lane, p, old, nv, pinfo, nodes(), outnz, inplus, raises);
-      reinterpret_cast<uint4 *>(rec->features)[lane] = __builtin_bit_cast(uint4, f);
-    }
     if (lane == 0) {
+      bool raises;
+      uint4 w[4];
+      move_feature_words(p, old, nv, pinfo, nodes(), outnz, inplus, raises, w);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) reinterpret_cast<uint4 *>(rec->features)[q] = w[q];
       rec->param = p;
       rec->value = nv;
       rec->delta = feasible ? delta : 0;

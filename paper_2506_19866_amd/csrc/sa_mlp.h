@@ -43,6 +43,10 @@ __device__ __forceinline__ v4f mfma_bf16(v8bf a, v8bf b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
+// max(z, 0) for finite z in one v_med3_f32 (fmaxf also canonicalises its
+// operand, a second instruction per value)
+__device__ __forceinline__ float relu(float z) { return __builtin_amdgcn_fmed3f(z, 0.f, 3.0e38f); }
+
 // Score of move l%16 (every lane) from its features 8g .. 8g+7 (feat), with
 // the fragments in LDS.
 __device__ __forceinline__ float mlp_tile_logit(v8bf feat, const uint4 *w1f, const uint4 *w2f, int lane, float b2) {
@@ -56,8 +60,8 @@ __device__ __forceinline__ float mlp_tile_logit(v8bf feat, const uint4 *w1f, con
     v8bf h;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      h[i] = (__bf16)fmaxf(z0[i], 0.f);
-      h[4 + i] = (__bf16)fmaxf(z1[i], 0.f);
+      h[i] = (__bf16)relu(z0[i]);
+      h[4 + i] = (__bf16)relu(z1[i]);
     }
     out = mfma_bf16(as_v8bf(w2f[u * 4 + g]), h, out);
   }
