@@ -146,14 +146,37 @@ def bench_batch(args) -> int:
 
 
 def _curve(run, sched_L, n):
-    """(cumulative stage-kernel seconds, global best after each stage)."""
+    """(cumulative stage-kernel seconds, global best after each stage,
+    fraction of steps that were accepted improving moves)."""
     st = run.stats()
     ms = run.stage_times_ms().astype(np.float64)
-    return np.cumsum(ms) * 1e-3, np.minimum.accumulate(st["best_cost"].astype(np.int64))
+    improving = (st["accepted"] - st["uphill"] - st["neutral"]).astype(np.float64).sum()
+    return (np.cumsum(ms) * 1e-3, np.minimum.accumulate(st["best_cost"].astype(np.int64)),
+            float(improving / (n * sched_L * len(ms))))
+
+
+def _auc(score, label) -> float:
+    """Probability that a random positive row outranks a random negative one
+    (ties count half): the Mann-Whitney statistic."""
+    order = np.argsort(score, kind="mergesort")
+    ranks = np.empty(len(score), dtype=np.float64)
+    s_sorted = score[order]
+    i = 0
+    while i < len(score):
+        j = i
+        while j + 1 < len(score) and s_sorted[j + 1] == s_sorted[i]:
+            j += 1
+        ranks[order[i:j + 1]] = 0.5 * (i + j) + 1
+        i = j + 1
+    pos = label > 0.5
+    n1, n0 = int(pos.sum()), int((~pos).sum())
+    if n1 == 0 or n0 == 0:
+        return float("nan")
+    return float((ranks[pos].sum() - n1 * (n1 + 1) / 2) / (n1 * n0))
 
 
 def _time_to(curve, target):
-    t, best = curve
+    t, best, _ = curve
     hit = np.flatnonzero(best <= target)
     return float(t[hit[0]]) if hit.size else None
 
@@ -167,10 +190,10 @@ def bench_learned(args) -> int:
     the cost of the generating parameters on the noisy data."""
     import torch
     from paper_2506_19866_amd import proposal, sa, synth
-    p2, s2 = synth.load_workload("c2"), synth.bench_schedule("c2")
+    p2, s2 = synth.load_workload(args.trace_workload), synth.bench_schedule(args.trace_workload)
     P2 = sa.Problem(p2)
     n2, L2 = s2["n_chains"], s2["steps_per_stage"]
-    x2 = torch.from_numpy(synth.start_vectors("c2", p2, n2)).cuda()
+    x2 = torch.from_numpy(synth.start_vectors(args.trace_workload, p2, n2)).cuda()
     te = max(1, (n2 * s2["n_stages"] * L2) // args.trace_rows)
     t0 = time.perf_counter()
     X, y, _ = proposal.collect(P2, x2, seed=s2["seed"], T0=s2["T0"], rho=s2["rho"], n_stages=s2["n_stages"],
@@ -178,13 +201,19 @@ def bench_learned(args) -> int:
     torch.cuda.synchronize()
     t_collect = time.perf_counter() - t0
     pos = float(y.mean().item())
-    log(f"[learned] traces: {X.shape[0]} rows from c2 (every {te}th step), {pos:.4f} improving, {t_collect:.2f} s")
+    log(f"[learned] traces: {X.shape[0]} rows from {args.trace_workload} (every {te}th step), {pos:.4f} improving, "
+        f"{t_collect:.2f} s")
+    # hold out every tenth row (by position) to measure how well the network ranks moves
+    held = torch.arange(X.shape[0], device=X.device) % 10 == 9
+    Xt, yt, Xh, yh = X[~held].contiguous(), y[~held].contiguous(), X[held].contiguous(), y[held].contiguous()
     net = sa.Mlp(proposal.init_params(args.model_seed))
     t0 = time.perf_counter()
-    losses = proposal.train(net, X, y, epochs=args.epochs, batch=8192, lr=args.lr, seed=args.model_seed, log=log)
+    losses = proposal.train(net, Xt, yt, epochs=args.epochs, batch=8192, lr=args.lr, seed=args.model_seed, log=log)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    del X, y
+    auc = _auc(net.forward(Xh).float().cpu().numpy(), yh.cpu().numpy())
+    log(f"[learned] held-out rows: {Xh.shape[0]}, ranking AUC of improving moves {auc:.3f}")
+    del X, y, Xt, yt, Xh, yh
 
     p3, s3 = synth.load_workload("c3"), synth.bench_schedule("c3")
     P3 = sa.Problem(p3)
@@ -201,7 +230,8 @@ def bench_learned(args) -> int:
             curves[kind].append(_curve(run, L3, n3))
             run.close()
             log(f"[learned] seed {seed} {kind}: final best {int(curves[kind][-1][1][-1])} "
-                f"in {curves[kind][-1][0][-1]:.2f} s of stage kernels")
+                f"in {curves[kind][-1][0][-1]:.2f} s of stage kernels, "
+                f"{curves[kind][-1][2]:.5f} of steps accepted improving moves")
     finals = {k: [int(c[1][-1]) for c in v] for k, v in curves.items()}
     target = int(np.median(finals["plain"]))
     tt = {k: [_time_to(c, target) for c in v] for k, v in curves.items()}
@@ -209,23 +239,29 @@ def bench_learned(args) -> int:
     total = {k: [float(c[0][-1]) for c in v] for k, v in curves.items()}
 
     def med(vals):
-        vals = [v for v in vals if v is not None]
-        return float(np.median(vals)) if vals else None
+        """Median with runs that never reach the target counted as infinitely
+        slow (None when that median is infinite)."""
+        m = float(np.median([np.inf if v is None else v for v in vals]))
+        return m if np.isfinite(m) else None
     value = med(tt["learned"])
     out = {
         "metric": "c3 time to the plain runs' median final cost, learned proposal", "value": value, "unit": "s",
         "n_gpus": 1, "steps": S3, "warmup": 0, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "int8 simulation, bf16 network",
-        "data": "synthetic (traces from c2 plain runs; evaluation on the stored c3 workload)",
+        "data": f"synthetic (traces from {args.trace_workload} plain runs; evaluation on the stored c3 workload)",
         "config": {"workload": f"c3 ({n3} chains x {L3} steps x {S3} stages), network trained on {te}-strided "
-                               f"traces of c2 plain runs", "refresh_every": args.refresh, "eps_plain": args.eps,
+                               f"traces of {args.trace_workload} plain runs", "refresh_every": args.refresh,
+                   "eps_plain": args.eps,
                    "eval_seeds": args.eval_seeds, "epochs": args.epochs},
         "plain_time_to_target_s": tt["plain"], "learned_time_to_target_s": tt["learned"],
         "plain_median_s": med(tt["plain"]), "target_cost": target,
+        "reached": {k: sum(v is not None for v in vals) for k, vals in tt.items()},
+        "final_best_median": {k: float(np.median(v)) for k, v in finals.items()},
         "hidden_params_cost": hidden_cost, "plain_time_to_hidden_s": th["plain"],
         "learned_time_to_hidden_s": th["learned"], "final_best": finals,
         "schedule_stage_kernel_s": total, "trace_collect_s": t_collect, "train_s": t_train,
-        "train_epoch_losses": losses, "improving_fraction": pos,
+        "train_epoch_losses": losses, "improving_fraction": pos, "held_out_auc": auc,
+        "improving_steps_fraction": {k: [c[2] for c in v] for k, v in curves.items()},
     }
     print(json.dumps(out), flush=True)
     net.close()
@@ -276,6 +312,7 @@ def main() -> int:
                          "learned-cost: per-stage cost of the learned kernel against the plain one on c3")
     ap.add_argument("--refresh-list", type=int, nargs="+", default=[16, 64, 256])
     ap.add_argument("--trace-rows", type=int, default=1 << 20)
+    ap.add_argument("--trace-workload", default="c2", choices=["c1", "c2", "c3"])
     ap.add_argument("--epochs", type=int, default=4)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--refresh", type=int, default=16)

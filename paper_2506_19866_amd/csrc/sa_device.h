@@ -282,7 +282,9 @@ __device__ __forceinline__ void time_step(const ATile<NM, NK> &A, const v4i (&B)
     const uint32_t s = (uint32_t)B[mt >> 2][mt & 3];
     const uint32_t cm = (uint32_t)CM[mt >> 2][mt & 3];
     const uint32_t k = pack_targets(acc);
-    const uint32_t target = k ^ ((k ^ s) & cm);  // cm ? s : k, one 3-input bit operation
+    // cm ? s : k bitwise, one v_bitop3_b32 (truth table indexed by
+    // (k << 2) | (s << 1) | cm: set for 3, 4, 6, 7)
+    const uint32_t target = __builtin_amdgcn_bitop3_b32(k, s, cm, 0xD8);
     NB[mt >> 2][mt & 3] = (int)(D == 1 ? step_one_level(target, s) : target);
   });
   // dwords without an m-tile (slots beyond the rows) carry over unchanged

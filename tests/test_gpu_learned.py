@@ -120,6 +120,7 @@ def _starts(prob, n, seed):
     (42, 20, 82, 8, 15, 4, 10, 1, 1),    # c2-like
     (43, 70, 300, 20, 9, 4, 25, 2, 1),   # two k-tiles, two condition groups, d = 2
     (44, 15, 40, 3, 8, 2, 5, 1, 0),      # penalty mode
+    (46, 127, 420, 5, 6, 3, 30, 1, 1),   # the largest learned layout (8 m-tiles x 2 k-tiles)
 ])
 def test_trace_of_plain_run_matches_oracle(seed, N, E, C, T, K, O, d, hard):
     prob = _problem(seed, N, E, C, T, K, O, d=d, hard=hard)

@@ -182,6 +182,36 @@ def test_run_other_layouts(N, E, C, d):
     _compare_runs(prob, x0, 5, T0=1.5, rho=0.8, n_stages=3, L=45)
 
 
+@pytest.mark.parametrize("N,E,C,T,K,n,L", [
+    (30, 100, 64, 6, 7, 5, 33),     # 64 conditions = 4 condition groups; every time observed incl. t = 0
+    (191, 700, 3, 4, 2, 3, 20),     # the largest layout (12 m-tiles x 3 k-tiles)
+    (25, 70, 6, 9, 4, 1, 130),      # a single chain; L not a multiple of the 64-step Philox batch
+])
+def test_run_extreme_shapes(N, E, C, T, K, n, L):
+    prob, _ = random_problem(3000 + N + C, n_nodes=N, n_edges=E, n_cond=C, n_steps=T, n_times=K,
+                             n_obs=max(2, N // 4), noise=0.15, clamps=(0, 2), step_size=1)
+    if K == T + 1:
+        prob["obs_t"] = np.arange(T + 1, dtype=np.int32)
+    x0 = synth.feasible_params(np.random.default_rng(N + C), n, prob["row_ptr"], prob["src"])
+    _compare_runs(prob, x0, 11, T0=1.2, rho=0.7, n_stages=2, L=L)
+
+
+def test_no_stage_launched_has_no_best():
+    sa = _sa()
+    w = synth.load_workload("c1")
+    run = sa.Run(sa.Problem(w), _dev(synth.start_vectors("c1", w, 4)), seed=1, T0=1.0, rho=0.9, n_stages=2,
+                 steps_per_stage=10, launch=False)
+    with pytest.raises(sa.SAError) as e:
+        run.best()
+    assert e.value.code == sa.SA_ERR_ARG
+    assert run.stats()["best_cost"].size == 0
+    with pytest.raises(sa.SAError):
+        run.launch(3)   # beyond the schedule
+    run.launch(2)
+    assert run.stats()["best_cost"].size == 2
+    run.close()
+
+
 def test_infeasible_start_is_rejected():
     sa = _sa()
     w = synth.load_workload("c1")
