@@ -9,7 +9,7 @@
  * shares no code, header, table or constant generator with the GPU library:
  * every definition below is written out again from the paper.
  *
- * Readings of the paper taken here (all listed in the design doc):
+ * Readings of the paper taken here:
  *   - update scheme: synchronous, every node moves from the states of the
  *     previous time step (the alternative named in §2.2);
  *   - parameters: x = [a_e for every edge, in-CSR order] ++ [theta_i per node],
