@@ -275,3 +275,17 @@ def test_collect_and_train_pipeline():
     losses = proposal.train(net, X, y, epochs=3, batch=512, lr=3e-3, seed=0)
     assert losses[-1] < losses[0]
     net.close()
+
+
+def test_learned_run_captured_in_a_graph():
+    """All stages of a learned run captured in one hipGraph give the same run."""
+    prob = _problem(59, 16, 50, 4, 10, 3, 6)
+    x0 = _starts(prob, 8, 4)
+    model = _dyadic_model(59)
+    kw = dict(seed=12, T0=1.0, rho=0.6, n_stages=3, steps_per_stage=40, model=model, refresh_every=8,
+              eps_plain=0.2)
+    eager = _gpu_run(prob, x0, **kw)
+    graph = _gpu_run(prob, x0, use_graph=True, **kw)
+    assert graph["stats"]["best_cost"].tolist() == eager["stats"]["best_cost"].tolist()
+    assert graph["stats"]["accepted"].tolist() == eager["stats"]["accepted"].tolist()
+    assert np.array_equal(graph["x"], eager["x"])
