@@ -182,11 +182,13 @@ extern "C" int sa_create_problem(const sa_problem_desc *d, sa_problem **out) {
   const long long max_cost = 2 * wsum + lambda * 2 * (long long)N;
   if (max_cost >= (1ll << 31) - 1) return fail(SA_ERR_OVERFLOW, "largest cost %lld does not fit int32", max_cost);
 
-  // tiles: nm m-tiles of 16 rows hold the nodes, nk k-tiles of 64 columns hold nodes + bias
+  // tiles: nm m-tiles of 16 rows hold the nodes, nk k-fragments of 128
+  // columns (32 slots per lane group) hold nodes + bias; layouts with two
+  // fragments start at 9 m-tiles
+  const int nk = N / 128 + 1;
   int nm = (N + 15) / 16;
-  if (N + 1 > 64 * ((nm + 3) / 4)) ++nm;
-  const int nk = (nm + 3) / 4;
-  if (nm > sa::kMaxTilesM) return fail(SA_ERR_UNSUPPORTED, "n_nodes %d > 191", N);
+  if (nk == 2 && nm < 9) nm = 9;
+  if (N > 191 || nm > sa::kMaxTilesM) return fail(SA_ERR_UNSUPPORTED, "n_nodes %d > 191", N);
   const int CG = (C + 15) / 16;
   if (CG > sa::kMaxCondGroups) return fail(SA_ERR_UNSUPPORTED, "n_conditions %d > 64", C);
 
@@ -200,7 +202,7 @@ extern "C" int sa_create_problem(const sa_problem_desc *d, sa_problem **out) {
   for (int v = 0; v < N; ++v)
     if (obs_index[v] < 0) order.push_back(v);
   std::vector<int> sg(N), sq(N);
-  const int slots = 16 * nk;
+  const int slots = 32 * nk;
   std::vector<int16_t> slot_node((size_t)4 * slots, -1);
   for (int k = 0; k < N; ++k) {
     const int v = order[k];
@@ -210,7 +212,7 @@ extern "C" int sa_create_problem(const sa_problem_desc *d, sa_problem **out) {
   }
   const int gb = N % 4, qb = N / 4;
   int nd = 1;
-  for (int o = 0; o < O; ++o) nd = std::max(nd, sq[d->obs_nodes[o]] / 4 + 1);
+  for (int o = 0; o < O; ++o) nd = std::max(nd, sq[d->obs_nodes[o]] / 8 + 1);
 
   // A entry of parameter p: row of its target node i, column of its source
   // node j (edge) or of the bias (theta_i)
@@ -218,9 +220,9 @@ extern "C" int sa_create_problem(const sa_problem_desc *d, sa_problem **out) {
   std::vector<int32_t> edst(E), esrc(E);
   auto place = [&](int p, int i, int colg, int colq) {
     const int lane = (4 * sg[i] + sq[i] % 4) + 16 * colg;
-    const int mt = sq[i] / 4, kt = colq / 16, dw = (colq % 16) / 4, b = colq % 4;
-    param_pos[p] = (uint32_t)lane | ((uint32_t)mt << 8) | ((uint32_t)kt << 12) | ((uint32_t)dw << 14) |
-                   ((uint32_t)b << 16);
+    const int mt = sq[i] / 4, kf = colq / 32, dw = (colq % 32) / 8, n = colq % 8;
+    param_pos[p] = (uint32_t)lane | ((uint32_t)mt << 8) | ((uint32_t)kf << 12) | ((uint32_t)dw << 14) |
+                   ((uint32_t)n << 16);
   };
   for (int i = 0; i < N; ++i)
     for (int e = d->in_row_ptr[i]; e < d->in_row_ptr[i + 1]; ++e) {
@@ -248,8 +250,8 @@ extern "C" int sa_create_problem(const sa_problem_desc *d, sa_problem **out) {
       const int c = cg * 16 + lane % 16, g = lane / 16;
       for (int q4 = 0; q4 < Q4; ++q4) {
         uint32_t vb = 0, vm = 0;
-        for (int b = 0; b < 4; ++b) {
-          const int q = q4 * 4 + b;
+        for (int b = 0; b < 8; ++b) {
+          const int q = q4 * 8 + b;
           const int v = slot_node[(size_t)g * slots + q];
           int val = 0, held = 1;
           if (c < C && g == gb && q == qb) {
@@ -263,8 +265,8 @@ extern "C" int sa_create_problem(const sa_problem_desc *d, sa_problem **out) {
               held = 0;
             }
           }
-          vb |= (uint32_t)val << (8 * b);
-          vm |= (held ? 0xffu : 0u) << (8 * b);
+          vb |= (uint32_t)val << (4 * b);
+          vm |= (held ? 0xfu : 0u) << (4 * b);
         }
         const size_t at = ((size_t)cg * Q4 + q4) * 64 + lane;
         b0[at] = vb;
@@ -274,12 +276,12 @@ extern "C" int sa_create_problem(const sa_problem_desc *d, sa_problem **out) {
       for (int k = 0; k < K; ++k)
         for (int q4 = 0; q4 < nd; ++q4) {
           uint32_t vr = 0, vw = 0;
-          for (int b = 0; b < 4; ++b) {
-            const int v = slot_node[(size_t)g * slots + q4 * 4 + b];
+          for (int b = 0; b < 8; ++b) {
+            const int v = slot_node[(size_t)g * slots + q4 * 8 + b];
             if (v < 0 || obs_index[v] < 0) continue;
             const size_t at = ((size_t)c * K + k) * O + obs_index[v];
-            vr |= (uint32_t)d->observed[at] << (8 * b);
-            vw |= (uint32_t)W[at] << (8 * b);
+            vr |= (uint32_t)d->observed[at] << (4 * b);
+            vw |= (uint32_t)W[at] << (4 * b);
           }
           const size_t at = (((size_t)cg * K + k) * nd + q4) * 64 + lane;
           orr[at] = vr;

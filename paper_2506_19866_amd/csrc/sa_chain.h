@@ -113,7 +113,7 @@ __device__ __forceinline__ void run_chain(const DevProblem &pb, const ChainJob &
       const int delta = ccand - ccur;
       // Metropolis in fixed point: accept iff delta <= 0 or u32 < tau[delta]
       const bool accept = feasible && (delta <= 0 || (delta <= job.dcap && r2 < job.tau[delta]));
-      patch_a(A, reg, accept ? 0u : mask, ((uint32_t)(is_edge ? old : -old) & 0xffu) * kLowBits);
+      patch_a(A, reg, accept ? 0u : mask, param_bits(p, E, old));
       if constexpr (Hooks::kEnabled)
         hk->record(job.g0 + (uint64_t)(it0 + j), p, old, nv, feasible, delta, accept, source, outnz, inplus, lane);
       if (!feasible) {

@@ -14,15 +14,17 @@
 namespace sa {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
 constexpr int kWavesPerBlock = 4;
-constexpr uint32_t kLowBits = 0x01010101u;
+constexpr uint32_t kLowNibbles = 0x11111111u;
 
 __host__ __device__ inline int round4(int v) { return (v + 3) & ~3; }
 
-// (m-tiles, k-tiles) of every instantiated register layout: nk = ceil(nm/4)
-#define SA_FOR_TILES(X) X(1, 1) X(2, 1) X(3, 1) X(4, 1) X(5, 2) X(6, 2) X(7, 2) X(8, 2) X(9, 3) X(10, 3) X(11, 3) X(12, 3)
+// (m-tiles, k-fragments of 128) of every instantiated register layout
+#define SA_FOR_TILES(X) X(1, 1) X(2, 1) X(3, 1) X(4, 1) X(5, 1) X(6, 1) X(7, 1) X(8, 1) X(9, 2) X(10, 2) X(11, 2) X(12, 2)
 
 inline dim3 grid_for(int64_t n) { return dim3((unsigned)((n + kWavesPerBlock - 1) / kWavesPerBlock)); }
 
@@ -93,10 +95,11 @@ __device__ __forceinline__ void static_for(F &&f) {
 // ---------------------------------------------------------------------------
 // The chain's parameter matrix in registers
 // ---------------------------------------------------------------------------
-// A operand dword `reg` = (mt*NK + kt)*4 + dw (16 bytes per lane per
-// (m-tile, k-tile)) lives in chunk reg/16, element reg%16, so a fragment is
-// four consecutive registers of one 16-register tuple.  Byte b of dword dw
-// holds entry (row l%16 of m-tile mt, column of slot (l/16, 16*kt + 4*dw + b)).
+// A operand dword `reg` = (mt*NK + kf)*4 + dw (16 bytes = 32 nibbles per
+// lane per (m-tile, k-fragment)) lives in chunk reg/16, element reg%16, so a
+// fragment is four consecutive registers of one 16-register tuple.  Nibble n
+// of dword dw holds entry (row l%16 of m-tile mt, column of slot
+// (l/16, 32*kf + 8*dw + n)) as an fp4 (e2m1) code.
 // Each 16-register chunk is its own local variable in the kernel (declared by
 // SA_DECLARE_A): an access with a dynamic element index then stays inside one
 // small object that the compiler keeps in a register tuple.
@@ -136,13 +139,21 @@ __device__ __forceinline__ v16i &chunk(const ATile<NM, NK> &A) {
   ATile<NM, NK> NAME{{NAME##_c0, NAME##_c1, NAME##_c2, NAME##_c3, NAME##_c4, NAME##_c5, NAME##_c6, \
                       NAME##_c7, NAME##_c8}}
 
-template <int MT, int KT, int NM, int NK>
-__device__ __forceinline__ v4i afrag(const ATile<NM, NK> &A) {
-  constexpr int r0 = (MT * NK + KT) * 4;
+// The A operand of m-tile MT, k-fragment KF, widened to the 8 dwords the
+// instruction takes (fp4 operands use the first 4).
+template <int MT, int KF, int NM, int NK>
+__device__ __forceinline__ v8i afrag(const ATile<NM, NK> &A) {
+  constexpr int r0 = (MT * NK + KF) * 4;
   const v16i &c = chunk<r0 / 16>(A);
   constexpr int o = r0 % 16;
-  return __builtin_shufflevector(c, c, o, o + 1, o + 2, o + 3);
+  return __builtin_shufflevector(c, c, o, o + 1, o + 2, o + 3, o, o + 1, o + 2, o + 3);
 }
+
+__device__ __forceinline__ v8i widen(v4i b) { return __builtin_shufflevector(b, b, 0, 1, 2, 3, 0, 1, 2, 3); }
+
+// fp4 (e2m1) code of a small integer a in [-2, 2]: magnitude 1 -> 0x2,
+// 2 -> 0x4, sign in bit 3
+__device__ __forceinline__ uint32_t fp4_code(int a) { return ((uint32_t)abs(a) << 1) | (a < 0 ? 8u : 0u); }
 
 // Replaces the bytes selected by `mask` (non-zero in one lane only) of A
 // register `reg` (wave-uniform) by `bits`.  Branch-free: every chunk does an
@@ -166,19 +177,24 @@ __device__ __forceinline__ void patch_a(ATile<NM, NK> &A, int reg, uint32_t mask
   });
 }
 
+// A entry of parameter p holding value v (edge value a, or -theta in the
+// bias column), replicated into every nibble.
+__device__ __forceinline__ uint32_t param_bits(int p, int E, int v) {
+  return fp4_code(p < E ? v : -v) * kLowNibbles;
+}
+
 // Writes parameter p's value v (edge value a, or theta) at its A position.
-// param_pos[p] = lane | m-tile << 8 | k-tile << 12 | dword << 14 | byte << 16,
-// independent of the register layout; the layout's NK turns it into the
-// A register index (mt*NK + kt)*4 + dw.
+// param_pos[p] = lane | m-tile << 8 | k-fragment << 12 | dword << 14 |
+// nibble << 16, independent of the register layout; the layout's NK turns it
+// into the A register index (mt*NK + kf)*4 + dw.
 template <int NK>
 __device__ __forceinline__ void param_patch_args(const DevProblem &pb, int lane, int p, int v, int &reg,
                                                  uint32_t &mask, uint32_t &bits) {
   const uint32_t pos = pb.param_pos[p];
-  const int a = p < pb.E ? v : -v;  // -theta in the bias column
-  const int mt = (int)((pos >> 8) & 15u), kt = (int)((pos >> 12) & 3u), dw = (int)((pos >> 14) & 3u);
-  reg = (mt * NK + kt) * 4 + dw;
-  mask = (lane == (int)(pos & 63u)) ? (0xffu << (8 * ((pos >> 16) & 3u))) : 0u;
-  bits = ((uint32_t)a & 0xffu) * kLowBits;
+  const int mt = (int)((pos >> 8) & 15u), kf = (int)((pos >> 12) & 3u), dw = (int)((pos >> 14) & 3u);
+  reg = (mt * NK + kf) * 4 + dw;
+  mask = (lane == (int)(pos & 63u)) ? (0xfu << (4 * ((pos >> 16) & 7u))) : 0u;
+  bits = param_bits(p, pb.E, v);
 }
 
 // A from a parameter vector: zero, then one patch per parameter.
@@ -198,35 +214,52 @@ __device__ __forceinline__ void build_a(ATile<NM, NK> &A, const DevProblem &pb, 
 }
 
 // ---------------------------------------------------------------------------
-// node update and score on packed states (4 conditions' bytes per dword)
+// node update and score on packed states: 8 nodes' fp4 codes per dword
 // ---------------------------------------------------------------------------
-// Packs clamp(t, 0, 2) of the four results of an m-tile into bytes: the
-// image bounded by the state range (§2.1, §2.2).  v_perm_b32 takes bytes 0-3
-// from its second operand and 4-7 from its first; 0x0c yields a zero byte.
-__device__ __forceinline__ uint32_t pack_targets(v4i acc) {
-  const uint32_t k0 = (uint32_t)min(max(acc[0], 0), 2);
-  const uint32_t k1 = (uint32_t)min(max(acc[1], 0), 2);
-  const uint32_t k2 = (uint32_t)min(max(acc[2], 0), 2);
-  const uint32_t k3 = (uint32_t)min(max(acc[3], 0), 2);
-  const uint32_t lo = __builtin_amdgcn_perm(k1, k0, 0x0c0c0400u);  // [k0, k1, 0, 0]
-  const uint32_t hi = __builtin_amdgcn_perm(k3, k2, 0x04000c0cu);  // [0, 0, k2, k3]
-  return lo | hi;
+// States are stored as the fp4 codes of s/2 (0, 0.5, 1.0 -> codes 0, 1, 2),
+// so a state's code is its value; the B operand's scale 2 restores s in the
+// product.  The bias input is a state fixed at 1.
+constexpr int kScaleOne = 127, kScaleTwo = 128;  // E8M0 scales 2^0, 2^1
+
+// The image of 16 rows for this lane's condition: K for rows 4g .. 4g+3.
+__device__ __forceinline__ v4f mfma_fp4(v8i a, v8i b, v4f acc) {
+  return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, acc, 4, 4, 0, kScaleOne, 0, kScaleTwo);
 }
 
-// d = 1: every byte moves one level towards its target, s' = s + sgn(k - s).
+// Writes the codes of clamp(K, 0, 2) of an m-tile's four rows into bytes
+// 2h and 2h+1 of `word` (h = m-tile parity): the image bounded by the state
+// range (§2.1, §2.2).  The conversion divides by its scale 2 and rounds to
+// fp4: 0, 1, 2 -> codes 0, 1, 2.
+__device__ __forceinline__ uint32_t put_targets(uint32_t word, const v4f &acc, int h) {
+  const float k0 = __builtin_amdgcn_fmed3f(acc[0], 0.f, 2.f), k1 = __builtin_amdgcn_fmed3f(acc[1], 0.f, 2.f);
+  const float k2 = __builtin_amdgcn_fmed3f(acc[2], 0.f, 2.f), k3 = __builtin_amdgcn_fmed3f(acc[3], 0.f, 2.f);
+  if (h == 0) {
+    word = __builtin_amdgcn_cvt_scalef32_pk_fp4_f32(word, k0, k1, 2.f, 0);
+    word = __builtin_amdgcn_cvt_scalef32_pk_fp4_f32(word, k2, k3, 2.f, 1);
+  } else {
+    word = __builtin_amdgcn_cvt_scalef32_pk_fp4_f32(word, k0, k1, 2.f, 2);
+    word = __builtin_amdgcn_cvt_scalef32_pk_fp4_f32(word, k2, k3, 2.f, 3);
+  }
+  return word;
+}
+
+// d = 1: every node moves one level towards its target, s' = s + sgn(k - s).
 // Over s, k in {0,1,2} the index s + 2k in [0, 6] determines s' uniquely:
 // index 0 1 2 3 4 5 6 -> 0 0 1 1 1 2 2 (pairs sharing an index agree, e.g.
-// (s,k) = (2,0) and (0,1) both give 1), so the update is one byte lookup
-// per condition, four per v_perm_b32.  k = s yields s (index 3s), which is
-// how clamped bytes are held.
+// (s,k) = (2,0) and (0,1) both give 1); k = s yields s (index 3s), which is
+// how clamped nodes are held.  The index is formed for all 8 nibbles at once
+// (no carries: nibbles <= 6), the even and odd nibbles are looked up as bytes
+// (v_perm_b32 takes bytes 0-3 from its second operand, 4-7 from its first).
 __device__ __forceinline__ uint32_t step_one_level(uint32_t k, uint32_t s) {
-  const uint32_t idx = (k << 1) + s;  // bytes <= 6: no carries between bytes
-  return __builtin_amdgcn_perm(0x00020201u, 0x01010000u, idx);
+  const uint32_t idx = (k << 1) + s;
+  const uint32_t lo = __builtin_amdgcn_perm(0x00020201u, 0x01010000u, idx & 0x0f0f0f0fu);
+  const uint32_t hi = __builtin_amdgcn_perm(0x00020201u, 0x01010000u, (idx >> 4) & 0x0f0f0f0fu);
+  return lo | (hi << 4);
 }
 
 // Weighted Manhattan distance of the packed states against the reference:
-// per byte |s - r| = x - 2*(x & x>>1) with x = s ^ r (s, r in {0,1,2}),
-// weighted by W (0 where the slot is not observed) with byte dot products.
+// per nibble |s - r| = x - 2*(x & x>>1) with x = s ^ r (s, r in {0,1,2}),
+// weighted by W (0 where the slot is not observed) with 4-bit dot products.
 // r and w point at this observed time's [nd][64] tables.
 template <int NK>
 __device__ __forceinline__ int score(const v4i (&B)[NK], const uint32_t *__restrict__ r,
@@ -239,8 +272,8 @@ __device__ __forceinline__ int score(const v4i (&B)[NK], const uint32_t *__restr
       const uint32_t x = s ^ r[q4 * kWave + lane];
       const uint32_t y = (x >> 1) & x;
       const uint32_t ww = w[q4 * kWave + lane];
-      a1 = __builtin_amdgcn_udot4(x, ww, a1, false);
-      a2 = __builtin_amdgcn_udot4(y, ww, a2, false);
+      a1 = __builtin_amdgcn_udot8(x, ww, a1, false);
+      a2 = __builtin_amdgcn_udot8(y, ww, a2, false);
     }
   }
   return (int)(a1 - 2u * a2);
@@ -254,55 +287,77 @@ __device__ __forceinline__ void write_states(const v4i (&B)[NK], const DevProble
 #pragma unroll
   for (int q4 = 0; q4 < 4 * NK; ++q4)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int v = pb.slot_node[g * 16 * NK + q4 * 4 + b];
+    for (int n = 0; n < 8; ++n) {
+      const int v = pb.slot_node[g * 32 * NK + q4 * 8 + n];
       if (v >= 0)
-        traj[((size_t)c * (pb.T + 1) + t) * pb.N + v] = (int8_t)(((uint32_t)B[q4 >> 2][q4 & 3] >> (8 * b)) & 0xffu);
+        traj[((size_t)c * (pb.T + 1) + t) * pb.N + v] = (int8_t)(((uint32_t)B[q4 >> 2][q4 & 3] >> (4 * n)) & 0xfu);
     }
 }
 
 // One synchronous time step (§2.2): every m-tile reads only the states of
-// step t-1 (B) and writes those of step t (NB).  Clamped bytes (mask CM) get
-// their old state as target, so they hold.  With RT only the first nm
-// m-tiles and nk k-tiles are present (a smaller network in a larger layout).
+// step t-1 (B) and writes those of step t (NB).  M-tile mt's four rows are
+// nibbles 4mt .. 4mt+3 of its lane group's slots, so two m-tiles fill one
+// dword, which then takes the clamp select (mask CM: clamped nodes get their
+// old state as target, so they hold) and the step.  With RT only the first nm
+// m-tiles and nk k-fragments are present (a smaller network in a larger
+// layout).
 template <int NM, int NK, int D, bool RT>
 __device__ __forceinline__ void time_step(const ATile<NM, NK> &A, const v4i (&B)[NK], v4i (&NB)[NK],
                                           const v4i (&CM)[NK], int nm, int nk) {
-  static_for<NM>([&](auto mtc) SA_INLINE {
-    constexpr int mt = decltype(mtc)::value;
-    if (RT && mt >= nm) {
-      NB[mt >> 2][mt & 3] = B[mt >> 2][mt & 3];
-      return;
-    }
-    v4i acc = {0, 0, 0, 0};
-    static_for<NK>([&](auto ktc) SA_INLINE {
-      constexpr int kt = decltype(ktc)::value;
-      if (!RT || kt < nk) acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(afrag<mt, kt>(A), B[kt], acc, 0, 0, 0);
+  v8i bw[NK];
+#pragma unroll
+  for (int kf = 0; kf < NK; ++kf) bw[kf] = widen(B[kf]);
+  constexpr int NW = (NM + 1) / 2;  // dwords holding m-tile rows
+  static_for<NW>([&](auto wc) SA_INLINE {
+    constexpr int w = decltype(wc)::value;
+    constexpr int kf = w / 4, dw = w % 4;
+    v4f acc[2];
+    static_for<2>([&](auto hc) SA_INLINE {
+      constexpr int h = decltype(hc)::value;
+      constexpr int mt = 2 * w + h;
+      acc[h] = v4f{0.f, 0.f, 0.f, 0.f};
+      if constexpr (mt < NM) {
+        if (!RT || mt < nm) {
+          static_for<NK>([&](auto kc) SA_INLINE {
+            constexpr int k = decltype(kc)::value;
+            if (!RT || k < nk) acc[h] = mfma_fp4(afrag<mt, k>(A), bw[k], acc[h]);
+          });
+        }
+      }
     });
-    const uint32_t s = (uint32_t)B[mt >> 2][mt & 3];
-    const uint32_t cm = (uint32_t)CM[mt >> 2][mt & 3];
-    const uint32_t k = pack_targets(acc);
-    // cm ? s : k bitwise, one v_bitop3_b32 (truth table indexed by
-    // (k << 2) | (s << 1) | cm: set for 3, 4, 6, 7)
-    const uint32_t target = __builtin_amdgcn_bitop3_b32(k, s, cm, 0xD8);
-    NB[mt >> 2][mt & 3] = (int)(D == 1 ? step_one_level(target, s) : target);
+    // The target word is built in the register of a spent result (no copy):
+    // bytes no m-tile writes hold no node and are held by CM.
+    uint32_t t = __builtin_bit_cast(uint32_t, acc[0][0]);
+    static_for<2>([&](auto hc) SA_INLINE {
+      constexpr int h = decltype(hc)::value;
+      constexpr int mt = 2 * w + h;
+      if constexpr (mt < NM) {
+        if (!RT || mt < nm) t = put_targets(t, acc[h], h);
+      }
+    });
+    const uint32_t s = (uint32_t)B[kf][dw];
+    const uint32_t cm = (uint32_t)CM[kf][dw];
+    // cm ? s : t bitwise, one v_bitop3_b32 (truth table indexed by
+    // (t << 2) | (s << 1) | cm: set for 3, 4, 6, 7)
+    const uint32_t target = __builtin_amdgcn_bitop3_b32(t, s, cm, 0xD8);
+    NB[kf][dw] = (int)(D == 1 ? step_one_level(target, s) : target);
   });
-  // dwords without an m-tile (slots beyond the rows) carry over unchanged
+  // dwords without m-tile rows (slots beyond the rows) carry over unchanged
   static_for<4 * NK>([&](auto qc) SA_INLINE {
     constexpr int q = decltype(qc)::value;
-    if constexpr (q >= NM) NB[q >> 2][q & 3] = B[q >> 2][q & 3];
+    if constexpr (q >= NW) NB[q >> 2][q & 3] = B[q >> 2][q & 3];
   });
   if constexpr (!RT) {
     // keep the whole step in one block and let the m-tiles' integer work run
     // under the next m-tile's matrix products
 #pragma unroll
-    for (int kt = 0; kt < NK; ++kt) asm volatile("" : "+v"(NB[kt]));
-    __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
-    static_for<NM - 1>([&](auto) SA_INLINE {
-      __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
-      __builtin_amdgcn_sched_group_barrier(0x002, 10, 0);
+    for (int kf = 0; kf < NK; ++kf) asm volatile("" : "+v"(NB[kf]));
+    __builtin_amdgcn_sched_group_barrier(0x008, 2 * NK, 0);
+    static_for<NW - 1>([&](auto) SA_INLINE {
+      __builtin_amdgcn_sched_group_barrier(0x008, 2 * NK, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, 16, 0);
     });
-    __builtin_amdgcn_sched_group_barrier(0x002, 12, 0);
+    __builtin_amdgcn_sched_group_barrier(0x002, 18, 0);
   }
 }
 
@@ -331,13 +386,13 @@ __device__ __forceinline__ int lane_mismatch(const ATile<NM, NK> &A, const DevPr
     const uint32_t *rbase = obs_r + (size_t)cg * pb.K * pb.nd * kWave;
     const uint32_t *wbase = obs_w + (size_t)cg * pb.K * pb.nd * kWave;
     int k = 0;
-    int tnext = pb.obs_t[0];
+    int tnext = uniform(pb.obs_t[0]);
     auto observe = [&](const v4i (&B)[NK], int t) SA_INLINE {
       if (TRAJ) write_states<NK>(B, pb, lane, c, t, traj);
       if (t == tnext) {
         total += score<NK>(B, rbase + (size_t)k * pb.nd * kWave, wbase + (size_t)k * pb.nd * kWave, pb.nd, lane);
         ++k;
-        tnext = k < pb.K ? pb.obs_t[k] : -1;
+        tnext = k < pb.K ? uniform(pb.obs_t[k]) : -1;
       }
     };
     observe(B0, 0);

@@ -1,59 +1,64 @@
 // sa_internal.h -- device-side problem layout shared by the host part of the
 // library (sa_api.hip) and its kernels (sa_k_batch.hip, sa_k_stage.hip).  Not a public header.
 //
-// Register-resident simulation on the int8 matrix cores of gfx950
-// ---------------------------------------------------------------
+// Register-resident simulation on the 4-bit matrix cores of gfx950
+// -----------------------------------------------------------------
 // One wavefront owns one chain.  The synchronous update of all nodes under 16
 // conditions at once is one product per time step,
 //     H[row(i)][c] = sum_j A[row(i)][col(j)] * S[col(j)][c],
 // where A holds the chain's edge values a_ji (and -theta_i in the column of a
-// constant "bias" input fixed at 1), and S the int8 states, one column per
-// condition.  It runs as v_mfma_i32_16x16x64_i8 tiles: A is the 16x64 A
-// operand of m-tile mt and k-tile kt, S the 64x16 B operand of k-tile kt.
+// constant "bias" input fixed at 1), and S the states, one column per
+// condition.  Every value involved is one of -2, -1, 0, 0.5, 1 (states are
+// held as s/2 and the B operand carries the scale 2), so both operands are
+// exact fp4 (e2m1) codes and the product runs as
+// v_mfma_scale_f32_16x16x128_f8f6f4 tiles with float32 results that are exact
+// small integers: A is the 16x128 A operand of m-tile mt and k-fragment kf,
+// S the 128x16 B operand of k-fragment kf.
 //
-// Lane l holds A rows l%16 and B/D columns l%16 (condition), and the k-range
-// of lane group g = l/16 (A and B share that k mapping).  The D result of
-// m-tile mt holds rows 4g + r (r = 0..3) in lane group g.  Each node gets one
-// "slot" (g, q): its state leaves the product in lane group g, m-tile q/4,
-// register r = q%4, and re-enters the next product as byte q%16 of k-tile
-// q/16 in the same lane group.  So the 4 results of m-tile mt pack into
-// exactly one dword of the next B operand (k-tile mt/4, dword mt%4) and the
-// whole trajectory stays in the lane's registers: no LDS, no cross-lane
-// traffic.
+// Lane l holds A rows l%16 and B/D columns l%16 (condition), and 32 nibbles
+// of the k-range of lane group g = l/16 (A and B share that k mapping).  The
+// D result of m-tile mt holds rows 4g + r (r = 0..3) in lane group g.  Each
+// node gets one "slot" (g, q): its state leaves the product in lane group g,
+// m-tile q/4, register r = q%4, and re-enters the next product as nibble q%32
+// of k-fragment q/32 in the same lane group.  So the 4 results of m-tile mt
+// pack into half a dword of the next B operand (k-fragment mt/8, dword
+// (mt%8)/2, bytes 2(mt%2) and 2(mt%2)+1) and the whole trajectory stays in the
+// lane's registers: no LDS, no cross-lane traffic.
 #pragma once
 #include <stdint.h>
 
 namespace sa {
 
 constexpr int kWave = 64;
-constexpr int kMaxTilesM = 12;  // N <= 191: 12 m-tiles, 3 k-tiles of 64
+constexpr int kMaxTilesM = 12;  // N <= 191: 12 m-tiles, 2 k-fragments of 128
 constexpr int kMaxCondGroups = 4;
 
 struct DevProblem {
   int32_t N, E, P, C, T, K, O;
   int32_t CG;      // condition groups of 16
-  int32_t nm, nk;  // m-tiles (16 rows) and k-tiles (64 columns)
-  int32_t nd;      // dwords per lane that hold observed slots
+  int32_t nm, nk;  // m-tiles (16 rows) and k-fragments (128 columns)
+  int32_t nd;      // dwords per lane (8 slots each) that hold observed slots
   int32_t d;       // step size
   int32_t hard;
   int32_t lambda;
-  // [P]: lane | m-tile << 8 | k-tile << 12 | dword << 14 | byte << 16 of the
-  // A entry of parameter p (independent of the register layout)
+  // [P]: lane | m-tile << 8 | k-fragment << 12 | dword << 14 | nibble << 16
+  // of the A entry of parameter p (independent of the register layout)
   const uint32_t *param_pos;
   const int32_t *edge_src, *edge_dst;  // [E]
   const int32_t *in_ptr;               // [N+1]
   const int32_t *out_ptr, *out_eid;    // [N+1], [E]: out-edges of each node (edge ids)
-  // [CG][4*nk dwords][64 lanes]: packed states at t = 0 (clamped nodes at
-  // their clamp value) and the mask of bytes that are held (clamped nodes,
-  // the bias slot, empty slots and lanes beyond the last condition)
+  // [CG][4*nk dwords][64 lanes]: packed state codes at t = 0 (clamped nodes
+  // at their clamp value) and the mask of nibbles that are held (clamped
+  // nodes, the bias slot, empty slots and lanes beyond the last condition)
   const uint32_t *b0, *cmask;
-  // [CG][K][nd dwords][64 lanes]: packed reference values and weights (0 where unobserved)
+  // [CG][K][nd dwords][64 lanes]: packed reference values and weights, a
+  // nibble per slot (weight 0 where unobserved)
   const uint32_t *obs_r, *obs_w;
   const int32_t *obs_t;                // [K]
-  const int16_t *slot_node;            // [4][16*nk]: node at (g, q), -1 bias/empty
+  const int16_t *slot_node;            // [4][32*nk]: node at (g, q), -1 bias/empty
   // learned proposal (networks up to 127 nodes)
   int32_t sum_w;                       // sum of all observation weights
-  const int16_t *node_slot;            // [N]: g * 16*nk + q of the node's slot
+  const int16_t *node_slot;            // [N]: g * 32*nk + q of the node's slot
   const int32_t *node_sw, *node_wr;    // [N]: sum of W and of W*R over the node's observations (0: unobserved)
   // [P]: target i | source j << 7 | in-degree(i) << 14 | out-degree(j) << 21 |
   // edge << 28 | observed(i) << 29 | observed(j) << 30 (j = 0 for a threshold)
@@ -150,14 +155,14 @@ int launch_simulate(const DevProblem &pb, const int8_t *x, int64_t n, int8_t *tr
 int launch_stage(const DevProblem &pb, const StageArgs &sa, void *stream);
 size_t stage_smem_bytes(const DevProblem &pb, int waves_per_block);
 int stage_waves_per_block(const DevProblem &pb);
-// Persistent launch of size class cls (layout (4,1), (8,2) or (10,3)) and step size d.
+// Persistent launch of size class cls (layout (4,1), (8,1) or (10,2)) and step size d.
 int launch_persistent(const BatchArgs &a, int cls, int d, int grid, size_t smem, void *stream);
 int persistent_class(int nm);
 int launch_batch_reduce(const BatchReduceArgs &ra, void *stream);
 size_t persistent_smem_bytes(const DevProblem &pb, int waves);
 // Workgroups of `waves` waves with `smem` bytes of LDS of class cls that fit on one CU.
 int persistent_blocks_per_cu(int cls, int waves, size_t smem);
-constexpr int kPersistentTilesM = 10, kPersistentTilesK = 3;  // networks up to 159 nodes
+constexpr int kPersistentTilesM = 10, kPersistentTilesK = 2;  // networks up to 159 nodes
 constexpr int kPersistentClasses = 3;
 constexpr int kPersistentQueues = 2 * kPersistentClasses;     // one work counter per (class, step size)
 int launch_learned_stage(const DevProblem &pb, const StageArgs &sa, const LearnedArgs &la, void *stream);

@@ -76,7 +76,7 @@ size_t learned_smem_bytes(const DevProblem &pb, bool model) {
          (size_t)4 * round4(pb.P) + (size_t)kWavesPerBlock * learned_wave_bytes(pb);
 }
 
-#define SA_LEARNED_TILES(X) X(1, 1) X(2, 1) X(3, 1) X(4, 1) X(5, 2) X(6, 2) X(7, 2) X(8, 2)
+#define SA_LEARNED_TILES(X) X(1, 1) X(2, 1) X(3, 1) X(4, 1) X(5, 1) X(6, 1) X(7, 1) X(8, 1)
 
 int learned_stage_prepare(const DevProblem &pb, size_t smem) {
   hipError_t e = hipErrorInvalidValue;

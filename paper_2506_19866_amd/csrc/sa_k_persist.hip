@@ -106,7 +106,7 @@ size_t persistent_smem_bytes(const DevProblem &pb, int waves) {
 }
 
 // size classes: (m-tiles, k-tiles) of the layout each class runs in
-#define SA_PERSISTENT_CLASSES(X) X(0, 4, 1) X(1, 8, 2) X(2, 10, 3)
+#define SA_PERSISTENT_CLASSES(X) X(0, 4, 1) X(1, 8, 1) X(2, 10, 2)
 
 int persistent_class(int nm) { return nm <= 4 ? 0 : nm <= 8 ? 1 : 2; }
 

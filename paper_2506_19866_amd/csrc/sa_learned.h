@@ -30,10 +30,10 @@
 
 namespace sa {
 
-// Table area of a wave: the 2P cumulative weights, or the 3 x 64*nk slot
+// Table area of a wave: the 2P cumulative weights, or the 3 x 128*nk slot
 // aggregates while a refresh runs.
 __host__ __device__ inline int learned_tbl_words(const DevProblem &pb) {
-  return 2 * pb.P > 3 * 64 * pb.nk ? 2 * pb.P : 3 * 64 * pb.nk;
+  return 2 * pb.P > 3 * 128 * pb.nk ? 2 * pb.P : 3 * 128 * pb.nk;
 }
 // Feature rows of 32 moves staged between their computation and the tiles.
 constexpr int kStageMoves = 32;
@@ -44,21 +44,22 @@ __host__ __device__ inline int learned_wave_bytes(const DevProblem &pb) {
   return chain_lds_bytes(pb) + round4(pb.P) + 4 * learned_tbl_words(pb) + 12 * round4(pb.N) + 64 * kStageMoves;
 }
 
-// bytewise w * v for bytes w <= 3, v <= 2 (products <= 6: no carries)
-__device__ __forceinline__ uint32_t bytes_mul_small(uint32_t w, uint32_t v) {
-  const uint32_t m1 = (v & kLowBits) * 0xffu, m2 = ((v >> 1) & kLowBits) * 0xffu;
+// nibble-wise w * v for nibbles w <= 3, v <= 2 (products <= 6: no carries)
+__device__ __forceinline__ uint32_t nib_mul_small(uint32_t w, uint32_t v) {
+  const uint32_t m1 = (v & kLowNibbles) * 0xfu, m2 = ((v >> 1) & kLowNibbles) * 0xfu;
   return (w & m1) + ((w << 1) & m2);
 }
 
 // The refresh simulation: simulates every condition for the vector in A and
 // adds, per slot, the states (agg[0]), W*S (agg[1]) and W*|S - R| (agg[2])
-// summed over observed times and conditions.  Per lane the sums stay in
-// bytes (at most 6 per observed time: K <= 42), then the 16 condition lanes
-// of a lane group are added in 16-bit halves.  Returns M = sum of W*|S - R|.
+// summed over observed times and conditions.  Per lane the sums of the even
+// and of the odd nibbles stay in bytes (at most 6 per observed time:
+// K <= 42), then the 16 condition lanes of a lane group are added in 16-bit
+// halves.  Returns M = sum of W*|S - R|.
 template <int NM, int NK, int D>
 __device__ __forceinline__ int refresh_simulation(const ATile<NM, NK> &A, const DevProblem &pb, int lane,
                                                   const uint32_t *obs_r, const uint32_t *obs_w, uint32_t *agg) {
-  constexpr int kSlots = 64 * NK;
+  constexpr int kSlots = 128 * NK;
   for (int i = lane; i < 3 * kSlots; i += kWave) agg[i] = 0u;
   wave_sync();
   const int g = lane >> 4;
@@ -75,26 +76,31 @@ __device__ __forceinline__ int refresh_simulation(const ATile<NM, NK> &A, const 
     const bool live = cg * 16 + (lane & 15) < pb.C;
     const uint32_t *rbase = obs_r + (size_t)cg * pb.K * pb.nd * kWave;
     const uint32_t *wbase = obs_w + (size_t)cg * pb.K * pb.nd * kWave;
-    uint32_t aS[4 * NK], aWS[4 * NK], aWA[4 * NK];
+    // [2 * q4 + parity]: sums of the even (0) and odd (1) nibbles of dword q4
+    uint32_t aS[8 * NK], aWS[8 * NK], aWA[8 * NK];
 #pragma unroll
-    for (int q = 0; q < 4 * NK; ++q) aS[q] = aWS[q] = aWA[q] = 0u;
-    int k = 0, tnext = pb.obs_t[0];
+    for (int q = 0; q < 8 * NK; ++q) aS[q] = aWS[q] = aWA[q] = 0u;
+    auto add_nibbles = [](uint32_t *acc, int q4, uint32_t v) SA_INLINE {
+      acc[2 * q4] += v & 0x0f0f0f0fu;
+      acc[2 * q4 + 1] += (v >> 4) & 0x0f0f0f0fu;
+    };
+    int k = 0, tnext = uniform(pb.obs_t[0]);
     auto observe = [&](const v4i (&B)[NK], int t) SA_INLINE {
       if (t != tnext) return;
 #pragma unroll
       for (int q4 = 0; q4 < 4 * NK; ++q4) {
         const uint32_t s = (uint32_t)B[q4 >> 2][q4 & 3];
-        if (live) aS[q4] += s;
+        if (live) add_nibbles(aS, q4, s);
         if (q4 < pb.nd) {
           const uint32_t r = rbase[((size_t)k * pb.nd + q4) * kWave + lane];
           const uint32_t w = wbase[((size_t)k * pb.nd + q4) * kWave + lane];
           const uint32_t x = s ^ r, y = (x >> 1) & x;
-          aWA[q4] += bytes_mul_small(w, x - 2u * y);
-          aWS[q4] += bytes_mul_small(w, s);
+          add_nibbles(aWA, q4, nib_mul_small(w, x - 2u * y));
+          add_nibbles(aWS, q4, nib_mul_small(w, s));
         }
       }
       ++k;
-      tnext = k < pb.K ? pb.obs_t[k] : -1;
+      tnext = k < pb.K ? uniform(pb.obs_t[k]) : -1;
     };
     observe(B0, 0);
     int t = 1;
@@ -108,6 +114,7 @@ __device__ __forceinline__ int refresh_simulation(const ATile<NM, NK> &A, const 
       time_step<NM, NK, D, false>(A, B0, B1, CM, NM, NK);
       observe(B1, t);
     }
+    // byte b of a parity-p accumulator holds nibble 2b + p: slot 8*q4 + 2b + p
     auto fold = [&](uint32_t v, uint32_t *dst) SA_INLINE {
       uint32_t lo = v & 0x00ff00ffu, hi = (v >> 8) & 0x00ff00ffu;
 #pragma unroll
@@ -117,18 +124,20 @@ __device__ __forceinline__ int refresh_simulation(const ATile<NM, NK> &A, const 
       }
       if ((lane & 15) == 0) {
         dst[0] += lo & 0xffffu;
-        dst[1] += hi & 0xffffu;
-        dst[2] += lo >> 16;
-        dst[3] += hi >> 16;
+        dst[2] += hi & 0xffffu;
+        dst[4] += lo >> 16;
+        dst[6] += hi >> 16;
       }
     };
 #pragma unroll
-    for (int q4 = 0; q4 < 4 * NK; ++q4) {
-      const int slot = g * 16 * NK + q4 * 4;
-      fold(aS[q4], agg + slot);
-      fold(aWS[q4], agg + kSlots + slot);
-      fold(aWA[q4], agg + 2 * kSlots + slot);
-    }
+    for (int q4 = 0; q4 < 4 * NK; ++q4)
+#pragma unroll
+      for (int par = 0; par < 2; ++par) {
+        const int slot = g * 32 * NK + q4 * 8 + par;
+        fold(aS[2 * q4 + par], agg + slot);
+        fold(aWS[2 * q4 + par], agg + kSlots + slot);
+        fold(aWA[2 * q4 + par], agg + 2 * kSlots + slot);
+      }
     wave_sync();
   }
   int m = 0;
@@ -139,7 +148,7 @@ __device__ __forceinline__ int refresh_simulation(const ATile<NM, NK> &A, const 
 // Per-node float features of the refresh from the slot aggregates.
 __device__ __forceinline__ void node_features(const DevProblem &pb, int lane, const uint32_t *agg, float *msh,
                                               float *eh, float *ah) {
-  const int slots = 64 * pb.nk;
+  const int slots = 128 * pb.nk;
   const float den_s = (float)(2 * pb.C * pb.K);
   for (int i = lane; i < pb.N; i += kWave) {
     const int s = pb.node_slot[i];
