@@ -131,7 +131,7 @@ def bench_batch(args) -> int:
     out = {
         "metric": "SA chain-steps/s, batched uneven networks", "value": value, "unit": "chain-steps/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed * 1e3 / args.steps,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int8",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp4",
         "data": "synthetic (seeded generator + oracle-simulated reference data, stored workload)",
         "config": {"workload": f"c4: {len(probs)} networks of 10-150 nodes, {n} chains each x {L} steps per stage, "
                                f"one persistent launch per stage, stages in one hipGraph",
@@ -247,7 +247,7 @@ def bench_learned(args) -> int:
     out = {
         "metric": "c3 time to the plain runs' median final cost, learned proposal", "value": value, "unit": "s",
         "n_gpus": 1, "steps": S3, "warmup": 0, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-        "dtype": "int8 simulation, bf16 network",
+        "dtype": "fp4 simulation, bf16 network",
         "data": f"synthetic (traces from {args.trace_workload} plain runs; evaluation on the stored c3 workload)",
         "config": {"workload": f"c3 ({n3} chains x {L3} steps x {S3} stages), network trained on {te}-strided "
                                f"traces of {args.trace_workload} plain runs", "refresh_every": args.refresh,
@@ -373,6 +373,7 @@ def main() -> int:
     elapsed = time.perf_counter() - t0
     stats = run.stats()
     stage_ms = run.stage_times_ms()
+    info = run.info()
     _, best_cost, _ = run.best()
     chain_steps = n * L * args.steps
     value = chain_steps / elapsed
@@ -389,12 +390,13 @@ def main() -> int:
     launch_key = f"{name}:{n}x{L}"
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK_OPS / 1e12, "unit": "TOP/s",
                 "frac": achieved / ALU_PEAK_OPS, "traffic": traffic_from_profiles(launch_key),
-                "kernel": "stage_kernel<8,2,1>", "avg_launch_ms": float(np.mean(stage_ms)),
+                "kernel": f"stage_kernel<{info['tiles_m']},{info['frags_k']},{int(prob.get('step_size', 1))}>",
+                "avg_launch_ms": float(np.mean(stage_ms)),
                 "ops_per_launch": ops_per_launch}
     out = {
         "metric": "SA chain-steps/s at 723-param scale", "value": value, "unit": "chain-steps/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed * 1e3 / args.steps,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int8",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp4",
         "data": "synthetic (seeded generator + oracle-simulated reference data, stored workload)",
         "config": {"workload": f"{name}: Mtb-scale, {prob['n_nodes']} nodes, {prob['n_edges']} edges, "
                                f"{prob['n_nodes'] + prob['n_edges']} ternary params, {prob['n_cond']} conditions, "

@@ -180,6 +180,8 @@ typedef struct {
   int32_t kernel;            /* SA_KERNEL_PERSISTENT when the many-network kernel runs */
   int32_t chains_per_block;  /* as chosen (by the autotuner when asked) */
   int32_t stages_launched;
+  int32_t tiles_m;           /* register layout of problem 0: m-tiles of 16 rows */
+  int32_t frags_k;           /* and k-fragments of 128 columns */
 } sa_run_info;
 
 /* Per temperature stage, per problem (before the global restart). */

@@ -265,7 +265,7 @@ extern "C" int sa_create_problem(const sa_problem_desc *d, sa_problem **out) {
               held = 0;
             }
           }
-          vb |= (uint32_t)val << (4 * b);
+          vb |= sa::state_code(val) << (4 * b);
           vm |= (held ? 0xfu : 0u) << (4 * b);
         }
         const size_t at = ((size_t)cg * Q4 + q4) * 64 + lane;
@@ -280,7 +280,7 @@ extern "C" int sa_create_problem(const sa_problem_desc *d, sa_problem **out) {
             const int v = slot_node[(size_t)g * slots + q4 * 8 + b];
             if (v < 0 || obs_index[v] < 0) continue;
             const size_t at = ((size_t)c * K + k) * O + obs_index[v];
-            vr |= (uint32_t)d->observed[at] << (4 * b);
+            vr |= sa::state_code(d->observed[at]) << (4 * b);
             vw |= (uint32_t)W[at] << (4 * b);
           }
           const size_t at = (((size_t)cg * K + k) * nd + q4) * 64 + lane;
@@ -966,6 +966,8 @@ extern "C" int sa_run_get_info(sa_run *r, sa_run_info *info) {
   info->kernel = r->persistent ? SA_KERNEL_PERSISTENT : SA_KERNEL_AUTO;
   info->chains_per_block = r->persistent ? r->waves : sa::stage_waves_per_block(r->probs[0]->dev);
   info->stages_launched = r->launched;
+  info->tiles_m = r->probs[0]->dev.nm;
+  info->frags_k = r->probs[0]->dev.nk;
   return SA_OK;
 }
 

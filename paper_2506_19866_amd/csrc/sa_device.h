@@ -151,9 +151,12 @@ __device__ __forceinline__ v8i afrag(const ATile<NM, NK> &A) {
 
 __device__ __forceinline__ v8i widen(v4i b) { return __builtin_shufflevector(b, b, 0, 1, 2, 3, 0, 1, 2, 3); }
 
-// fp4 (e2m1) code of a small integer a in [-2, 2]: magnitude 1 -> 0x2,
-// 2 -> 0x4, sign in bit 3
-__device__ __forceinline__ uint32_t fp4_code(int a) { return ((uint32_t)abs(a) << 1) | (a < 0 ? 8u : 0u); }
+// fp4 (e2m1) code of a small integer a in [-3, 3]: magnitude 1 -> 0x2,
+// 2 -> 0x4, 3 -> 0x5, sign in bit 3
+__device__ __forceinline__ uint32_t fp4_code(int a) {
+  const uint32_t m = (uint32_t)abs(a);
+  return (m == 3u ? 0x5u : m << 1) | (a < 0 ? 8u : 0u);
+}
 
 // Replaces the bytes selected by `mask` (non-zero in one lane only) of A
 // register `reg` (wave-uniform) by `bits`.  Branch-free: every chunk does an
@@ -177,10 +180,10 @@ __device__ __forceinline__ void patch_a(ATile<NM, NK> &A, int reg, uint32_t mask
   });
 }
 
-// A entry of parameter p holding value v (edge value a, or -theta in the
-// bias column), replicated into every nibble.
+// A entry of parameter p holding value v (edge value a, or -theta - 1 in the
+// bias column: the product is h - 1), replicated into every nibble.
 __device__ __forceinline__ uint32_t param_bits(int p, int E, int v) {
-  return fp4_code(p < E ? v : -v) * kLowNibbles;
+  return fp4_code(p < E ? v : -v - 1) * kLowNibbles;
 }
 
 // Writes parameter p's value v (edge value a, or theta) at its A position.
@@ -216,51 +219,63 @@ __device__ __forceinline__ void build_a(ATile<NM, NK> &A, const DevProblem &pb, 
 // ---------------------------------------------------------------------------
 // node update and score on packed states: 8 nodes' fp4 codes per dword
 // ---------------------------------------------------------------------------
-// States are stored as the fp4 codes of s/2 (0, 0.5, 1.0 -> codes 0, 1, 2),
-// so a state's code is its value; the B operand's scale 2 restores s in the
-// product.  The bias input is a state fixed at 1.
-constexpr int kScaleOne = 127, kScaleTwo = 128;  // E8M0 scales 2^0, 2^1
+// States are stored as the fp4 codes of 2s (0, 2.0, 4.0 -> codes 0x0, 0x4,
+// 0x6), a thermometer code: bit 2 = [s >= 1], bit 1 = [s >= 2].  The B
+// operand's scale 2^-1 restores s in the product.  The bias input is a state
+// fixed at 1.
+constexpr int kScaleOne = 127, kScaleHalf = 126;  // E8M0 scales 2^0, 2^-1
+constexpr uint32_t kBit2 = 0x44444444u;           // bit 2 of every nibble
 
-// The image of 16 rows for this lane's condition: K for rows 4g .. 4g+3.
+// Rows 4g .. 4g+3 of an m-tile for this lane's condition: h - 1.
 __device__ __forceinline__ v4f mfma_fp4(v8i a, v8i b, v4f acc) {
-  return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, acc, 4, 4, 0, kScaleOne, 0, kScaleTwo);
+  return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, acc, 4, 4, 0, kScaleOne, 0, kScaleHalf);
 }
 
-// Writes the codes of clamp(K, 0, 2) of an m-tile's four rows into bytes
-// 2h and 2h+1 of `word` (h = m-tile parity): the image bounded by the state
-// range (§2.1, §2.2).  The conversion divides by its scale 2 and rounds to
-// fp4: 0, 1, 2 -> codes 0, 1, 2.
-__device__ __forceinline__ uint32_t put_targets(uint32_t word, const v4f &acc, int h) {
-  const float k0 = __builtin_amdgcn_fmed3f(acc[0], 0.f, 2.f), k1 = __builtin_amdgcn_fmed3f(acc[1], 0.f, 2.f);
-  const float k2 = __builtin_amdgcn_fmed3f(acc[2], 0.f, 2.f), k3 = __builtin_amdgcn_fmed3f(acc[3], 0.f, 2.f);
+// Writes the fp4 codes of 8x for an m-tile's four results x = h - 1 into
+// bytes 2h and 2h+1 of `word` (h = m-tile parity).  The conversion saturates
+// at 6, so every code is 0x0 (x = 0), 0x7 (x >= 1) or 0xf (x <= -1) (0x8 if a
+// zero ever carried a sign): bit 3 = [x < 0], bit 2 = [x != 0].  With
+// t = clamp(h, 0, 2) (§2.1, §2.2): [t >= 2] = bit 2 and not bit 3,
+// [t >= 1] = not (bit 2 and bit 3).
+__device__ __forceinline__ uint32_t put_codes(uint32_t word, const v4f &acc, int h) {
+  constexpr float kSaturate = 0.125f;  // the conversion divides by it
   if (h == 0) {
-    word = __builtin_amdgcn_cvt_scalef32_pk_fp4_f32(word, k0, k1, 2.f, 0);
-    word = __builtin_amdgcn_cvt_scalef32_pk_fp4_f32(word, k2, k3, 2.f, 1);
+    word = __builtin_amdgcn_cvt_scalef32_pk_fp4_f32(word, acc[0], acc[1], kSaturate, 0);
+    word = __builtin_amdgcn_cvt_scalef32_pk_fp4_f32(word, acc[2], acc[3], kSaturate, 1);
   } else {
-    word = __builtin_amdgcn_cvt_scalef32_pk_fp4_f32(word, k0, k1, 2.f, 2);
-    word = __builtin_amdgcn_cvt_scalef32_pk_fp4_f32(word, k2, k3, 2.f, 3);
+    word = __builtin_amdgcn_cvt_scalef32_pk_fp4_f32(word, acc[0], acc[1], kSaturate, 2);
+    word = __builtin_amdgcn_cvt_scalef32_pk_fp4_f32(word, acc[2], acc[3], kSaturate, 3);
   }
   return word;
 }
 
-// d = 1: every node moves one level towards its target, s' = s + sgn(k - s).
-// Over s, k in {0,1,2} the index s + 2k in [0, 6] determines s' uniquely:
-// index 0 1 2 3 4 5 6 -> 0 0 1 1 1 2 2 (pairs sharing an index agree, e.g.
-// (s,k) = (2,0) and (0,1) both give 1); k = s yields s (index 3s), which is
-// how clamped nodes are held.  The index is formed for all 8 nibbles at once
-// (no carries: nibbles <= 6), the even and odd nibbles are looked up as bytes
-// (v_perm_b32 takes bytes 0-3 from its second operand, 4-7 from its first).
-__device__ __forceinline__ uint32_t step_one_level(uint32_t k, uint32_t s) {
-  const uint32_t idx = (k << 1) + s;
-  const uint32_t lo = __builtin_amdgcn_perm(0x00020201u, 0x01010000u, idx & 0x0f0f0f0fu);
-  const uint32_t hi = __builtin_amdgcn_perm(0x00020201u, 0x01010000u, (idx >> 4) & 0x0f0f0f0fu);
-  return lo | (hi << 4);
+// Next states of 8 nodes from the codes w of x = h - 1 and the states s.
+// d = 1 moves one level towards t = clamp(h, 0, 2):
+//     [s' >= 1] = [t >= 1] or [s >= 2],   [s' >= 2] = [t >= 2] and [s >= 1];
+// d >= 2 reaches t: s' = t.  Both thresholds are formed at bit 2 of every
+// nibble, where w holds [x != 0], w >> 1 the sign of x, s [s >= 1] and
+// s << 1 [s >= 2]; [s' >= 2] then moves down to bit 1.  v_bitop3_b32 truth
+// tables are indexed by (a << 2) | (b << 1) | c.
+template <int D>
+__device__ __forceinline__ uint32_t next_states(uint32_t w, uint32_t s) {
+  const uint32_t u = w >> 1;
+  if constexpr (D == 1) {
+    const uint32_t ge1 = __builtin_amdgcn_bitop3_b32(u, w, s << 1, 0xBF);  // !(u & w) | c
+    const uint32_t ge2 = __builtin_amdgcn_bitop3_b32(w, u, s, 0x20);       // a & !b & c: bit 2 only
+    return __builtin_amdgcn_bitop3_b32(ge1, kBit2, ge2 >> 1, 0xEA);         // (a & b) | c
+  } else {
+    const uint32_t ge1 = __builtin_amdgcn_bitop3_b32(u, w, kBit2, 0x2A);   // !(a & b) & c
+    const uint32_t ge2 = __builtin_amdgcn_bitop3_b32(w, u, kBit2, 0x20);   // a & !b & c
+    return ge1 | (ge2 >> 1);
+  }
 }
 
 // Weighted Manhattan distance of the packed states against the reference:
-// per nibble |s - r| = x - 2*(x & x>>1) with x = s ^ r (s, r in {0,1,2}),
-// weighted by W (0 where the slot is not observed) with 4-bit dot products.
-// r and w point at this observed time's [nd][64] tables.
+// x = s ^ r has [s >= 1] != [r >= 1] at bit 2 and [s >= 2] != [r >= 2] at
+// bit 1, so |s - r| is the number of set bits; with 4-bit dot products
+// against W (0 where the slot is not observed), a1 = sum W (2 b1 + 4 b2) and
+// a2 = sum 4 W b2 give sum W (b1 + b2) = (2 a1 - a2) / 4.  r and w point at
+// this observed time's [nd][64] tables.
 template <int NK>
 __device__ __forceinline__ int score(const v4i (&B)[NK], const uint32_t *__restrict__ r,
                                      const uint32_t *__restrict__ w, int nd, int lane) {
@@ -268,15 +283,18 @@ __device__ __forceinline__ int score(const v4i (&B)[NK], const uint32_t *__restr
 #pragma unroll
   for (int q4 = 0; q4 < 4 * NK; ++q4) {
     if (q4 < nd) {
-      const uint32_t s = (uint32_t)B[q4 >> 2][q4 & 3];
-      const uint32_t x = s ^ r[q4 * kWave + lane];
-      const uint32_t y = (x >> 1) & x;
+      const uint32_t x = (uint32_t)B[q4 >> 2][q4 & 3] ^ r[q4 * kWave + lane];
       const uint32_t ww = w[q4 * kWave + lane];
       a1 = __builtin_amdgcn_udot8(x, ww, a1, false);
-      a2 = __builtin_amdgcn_udot8(y, ww, a2, false);
+      a2 = __builtin_amdgcn_udot8(x & kBit2, ww, a2, false);
     }
   }
-  return (int)(a1 - 2u * a2);
+  return (int)((2u * a1 - a2) >> 2);
+}
+
+// State values (0, 1, 2) of 8 packed codes, one per nibble.
+__device__ __forceinline__ uint32_t state_values(uint32_t s) {
+  return ((s >> 1) & kLowNibbles) + ((s >> 2) & kLowNibbles);
 }
 
 template <int NK>
@@ -290,7 +308,8 @@ __device__ __forceinline__ void write_states(const v4i (&B)[NK], const DevProble
     for (int n = 0; n < 8; ++n) {
       const int v = pb.slot_node[g * 32 * NK + q4 * 8 + n];
       if (v >= 0)
-        traj[((size_t)c * (pb.T + 1) + t) * pb.N + v] = (int8_t)(((uint32_t)B[q4 >> 2][q4 & 3] >> (4 * n)) & 0xfu);
+        traj[((size_t)c * (pb.T + 1) + t) * pb.N + v] =
+            (int8_t)((state_values((uint32_t)B[q4 >> 2][q4 & 3]) >> (4 * n)) & 0xfu);
     }
 }
 
@@ -325,22 +344,21 @@ __device__ __forceinline__ void time_step(const ATile<NM, NK> &A, const v4i (&B)
         }
       }
     });
-    // The target word is built in the register of a spent result (no copy):
+    // The code word is built in the register of a spent result (no copy):
     // bytes no m-tile writes hold no node and are held by CM.
-    uint32_t t = __builtin_bit_cast(uint32_t, acc[0][0]);
+    uint32_t x = __builtin_bit_cast(uint32_t, acc[0][0]);
     static_for<2>([&](auto hc) SA_INLINE {
       constexpr int h = decltype(hc)::value;
       constexpr int mt = 2 * w + h;
       if constexpr (mt < NM) {
-        if (!RT || mt < nm) t = put_targets(t, acc[h], h);
+        if (!RT || mt < nm) x = put_codes(x, acc[h], h);
       }
     });
     const uint32_t s = (uint32_t)B[kf][dw];
     const uint32_t cm = (uint32_t)CM[kf][dw];
-    // cm ? s : t bitwise, one v_bitop3_b32 (truth table indexed by
-    // (t << 2) | (s << 1) | cm: set for 3, 4, 6, 7)
-    const uint32_t target = __builtin_amdgcn_bitop3_b32(t, s, cm, 0xD8);
-    NB[kf][dw] = (int)(D == 1 ? step_one_level(target, s) : target);
+    // cm ? s : next bitwise, one v_bitop3_b32 (truth table indexed by
+    // (next << 2) | (s << 1) | cm: set for 3, 4, 6, 7)
+    NB[kf][dw] = (int)__builtin_amdgcn_bitop3_b32(next_states<D>(x, s), s, cm, 0xD8);
   });
   // dwords without m-tile rows (slots beyond the rows) carry over unchanged
   static_for<4 * NK>([&](auto qc) SA_INLINE {
@@ -352,12 +370,14 @@ __device__ __forceinline__ void time_step(const ATile<NM, NK> &A, const v4i (&B)
     // under the next m-tile's matrix products
 #pragma unroll
     for (int kf = 0; kf < NK; ++kf) asm volatile("" : "+v"(NB[kf]));
+    // integer instructions per dword: 4 conversions, the update, the select
+    constexpr int kValu = D == 1 ? 11 : 10;
     __builtin_amdgcn_sched_group_barrier(0x008, 2 * NK, 0);
     static_for<NW - 1>([&](auto) SA_INLINE {
       __builtin_amdgcn_sched_group_barrier(0x008, 2 * NK, 0);
-      __builtin_amdgcn_sched_group_barrier(0x002, 16, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, kValu, 0);
     });
-    __builtin_amdgcn_sched_group_barrier(0x002, 18, 0);
+    __builtin_amdgcn_sched_group_barrier(0x002, kValu + 2, 0);
   }
 }
 

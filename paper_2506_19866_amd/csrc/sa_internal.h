@@ -5,15 +5,16 @@
 // -----------------------------------------------------------------
 // One wavefront owns one chain.  The synchronous update of all nodes under 16
 // conditions at once is one product per time step,
-//     H[row(i)][c] = sum_j A[row(i)][col(j)] * S[col(j)][c],
-// where A holds the chain's edge values a_ji (and -theta_i in the column of a
-// constant "bias" input fixed at 1), and S the states, one column per
-// condition.  Every value involved is one of -2, -1, 0, 0.5, 1 (states are
-// held as s/2 and the B operand carries the scale 2), so both operands are
-// exact fp4 (e2m1) codes and the product runs as
+//     X[row(i)][c] = sum_j A[row(i)][col(j)] * S[col(j)][c] = h_i - 1,
+// where A holds the chain's edge values a_ji in {-1, 0, 1} (and -theta_i - 1
+// in {-3, -2, -1} in the column of a constant "bias" input fixed at 1), and S
+// the states, one column per condition.  States are held as 2s (codes 0x0,
+// 0x4, 0x6 of 0, 2.0, 4.0) and the B operand carries the scale 2^-1, so both
+// operands are exact fp4 (e2m1) codes and the product runs as
 // v_mfma_scale_f32_16x16x128_f8f6f4 tiles with float32 results that are exact
 // small integers: A is the 16x128 A operand of m-tile mt and k-fragment kf,
-// S the 128x16 B operand of k-fragment kf.
+// S the 128x16 B operand of k-fragment kf.  A state's code is a thermometer
+// code: bit 2 is [s >= 1], bit 1 is [s >= 2].
 //
 // Lane l holds A rows l%16 and B/D columns l%16 (condition), and 32 nibbles
 // of the k-range of lane group g = l/16 (A and B share that k mapping).  The
@@ -32,6 +33,9 @@ namespace sa {
 constexpr int kWave = 64;
 constexpr int kMaxTilesM = 12;  // N <= 191: 12 m-tiles, 2 k-fragments of 128
 constexpr int kMaxCondGroups = 4;
+
+// fp4 code of the state s in {0, 1, 2} (the value 2s)
+constexpr uint32_t state_code(int s) { return s == 0 ? 0u : (s == 1 ? 0x4u : 0x6u); }
 
 struct DevProblem {
   int32_t N, E, P, C, T, K, O;

@@ -89,13 +89,13 @@ __device__ __forceinline__ int refresh_simulation(const ATile<NM, NK> &A, const 
       if (t != tnext) return;
 #pragma unroll
       for (int q4 = 0; q4 < 4 * NK; ++q4) {
-        const uint32_t s = (uint32_t)B[q4 >> 2][q4 & 3];
+        const uint32_t code = (uint32_t)B[q4 >> 2][q4 & 3];
+        const uint32_t s = state_values(code);
         if (live) add_nibbles(aS, q4, s);
         if (q4 < pb.nd) {
           const uint32_t r = rbase[((size_t)k * pb.nd + q4) * kWave + lane];
           const uint32_t w = wbase[((size_t)k * pb.nd + q4) * kWave + lane];
-          const uint32_t x = s ^ r, y = (x >> 1) & x;
-          add_nibbles(aWA, q4, nib_mul_small(w, x - 2u * y));
+          add_nibbles(aWA, q4, nib_mul_small(w, state_values(code ^ r)));  // |S - R| per nibble
           add_nibbles(aWS, q4, nib_mul_small(w, s));
         }
       }

@@ -73,7 +73,7 @@ class _RunDesc(C.Structure):
 
 class _RunInfo(C.Structure):
     _fields_ = [("n_probs", C.c_int32), ("kernel", C.c_int32), ("chains_per_block", C.c_int32),
-                ("stages_launched", C.c_int32)]
+                ("stages_launched", C.c_int32), ("tiles_m", C.c_int32), ("frags_k", C.c_int32)]
 
 
 class _StageStats(C.Structure):

@@ -56,6 +56,7 @@ def test_persistent_kernel_on_one_network(chains_per_block):
     info = run.info()
     assert info["kernel"] == sa.SA_KERNEL_PERSISTENT
     assert info["chains_per_block"] in (1, 2, 4, 8)
+    assert (info["tiles_m"], info["frags_k"]) == (1, 1)   # 12 nodes
     if chains_per_block:
         assert info["chains_per_block"] == chains_per_block
     _check_against_oracle(run, [w], [x0], s["seed"], s["T0"], s["rho"], 6, 50)

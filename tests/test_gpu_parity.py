@@ -212,6 +212,22 @@ def test_no_stage_launched_has_no_best():
     run.close()
 
 
+@pytest.mark.parametrize("N,tiles", [(12, (1, 1)), (63, (4, 1)), (64, (4, 1)), (120, (8, 1)), (127, (8, 1)),
+                                     (128, (9, 2)), (150, (10, 2)), (191, (12, 2))])
+def test_register_layout_by_size(N, tiles):
+    """Register layout of the simulation: ceil(N/16) m-tiles of 16 rows and
+    N//128 + 1 k-fragments of 128 columns (nodes + bias), with at least 9
+    m-tiles once there are two fragments."""
+    sa = _sa()
+    prob, _ = random_problem(4000 + N, n_nodes=N, n_edges=3 * N, n_cond=4, n_steps=4, n_times=2,
+                             n_obs=max(2, N // 4), noise=0.0, clamps=(0, 1), step_size=1)
+    x0 = synth.feasible_params(np.random.default_rng(N), 2, prob["row_ptr"], prob["src"])
+    run = sa.Run(sa.Problem(prob), _dev(x0), seed=1, T0=1.0, rho=0.9, n_stages=1, steps_per_stage=4, launch=False)
+    info = run.info()
+    assert (info["tiles_m"], info["frags_k"]) == tiles
+    run.close()
+
+
 def test_infeasible_start_is_rejected():
     sa = _sa()
     w = synth.load_workload("c1")
