@@ -181,7 +181,7 @@ __device__ __forceinline__ void patch_a(ATile<NM, NK> &A, int reg, uint32_t mask
 }
 
 // A entry of parameter p holding value v (edge value a, or -theta - 1 in the
-// bias column: the product is h - 1), replicated into every nibble.
+// bias column: the product is 2(h - 1)), replicated into every nibble.
 __device__ __forceinline__ uint32_t param_bits(int p, int E, int v) {
   return fp4_code(p < E ? v : -v - 1) * kLowNibbles;
 }
@@ -220,20 +220,20 @@ __device__ __forceinline__ void build_a(ATile<NM, NK> &A, const DevProblem &pb, 
 // node update and score on packed states: 8 nodes' fp4 codes per dword
 // ---------------------------------------------------------------------------
 // States are stored as the fp4 codes of 2s (0, 2.0, 4.0 -> codes 0x0, 0x4,
-// 0x6), a thermometer code: bit 2 = [s >= 1], bit 1 = [s >= 2].  The B
-// operand's scale 2^-1 restores s in the product.  The bias input is a state
-// fixed at 1.
-constexpr int kScaleOne = 127, kScaleHalf = 126;  // E8M0 scales 2^0, 2^-1
-constexpr uint32_t kBit2 = 0x44444444u;           // bit 2 of every nibble
+// 0x6), a thermometer code: bit 2 = [s >= 1], bit 1 = [s >= 2].  The bias
+// input is a state fixed at 1, so the unscaled product is 2(h - 1).
+constexpr uint32_t kBit2 = 0x44444444u;  // bit 2 of every nibble
 
-// Rows 4g .. 4g+3 of an m-tile for this lane's condition: h - 1.
+// Rows 4g .. 4g+3 of an m-tile for this lane's condition: x = 2(h - 1).
+// Scale operands 0 select the unscaled form of the instruction (both scales
+// 1), which holds the VALU issue for fewer cycles than the scaled form.
 __device__ __forceinline__ v4f mfma_fp4(v8i a, v8i b, v4f acc) {
-  return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, acc, 4, 4, 0, kScaleOne, 0, kScaleHalf);
+  return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, acc, 4, 4, 0, 0, 0, 0);
 }
 
-// Writes the fp4 codes of 8x for an m-tile's four results x = h - 1 into
+// Writes the fp4 codes of 8x for an m-tile's four results x = 2(h - 1) into
 // bytes 2h and 2h+1 of `word` (h = m-tile parity).  The conversion saturates
-// at 6, so every code is 0x0 (x = 0), 0x7 (x >= 1) or 0xf (x <= -1) (0x8 if a
+// at 6, so every code is 0x0 (x = 0), 0x7 (x >= 2) or 0xf (x <= -2) (0x8 if a
 // zero ever carried a sign): bit 3 = [x < 0], bit 2 = [x != 0].  With
 // t = clamp(h, 0, 2) (§2.1, §2.2): [t >= 2] = bit 2 and not bit 3,
 // [t >= 1] = not (bit 2 and bit 3).
@@ -249,7 +249,7 @@ __device__ __forceinline__ uint32_t put_codes(uint32_t word, const v4f &acc, int
   return word;
 }
 
-// Next states of 8 nodes from the codes w of x = h - 1 and the states s.
+// Next states of 8 nodes from the codes w of x = 2(h - 1) and the states s.
 // d = 1 moves one level towards t = clamp(h, 0, 2):
 //     [s' >= 1] = [t >= 1] or [s >= 2],   [s' >= 2] = [t >= 2] and [s >= 1];
 // d >= 2 reaches t: s' = t.  Both thresholds are formed at bit 2 of every
@@ -384,6 +384,8 @@ __device__ __forceinline__ void time_step(const ATile<NM, NK> &A, const v4i (&B)
 // Simulates every condition for the chain whose parameters are in A and
 // returns this lane's share of the mismatch M (§2.3).  obs_r/obs_w:
 // [CG][K][nd][64] tables.  The two state buffers alternate between steps.
+// Without a trajectory to record, the simulation ends at the last observed
+// time (later states do not enter M).
 template <int NM, int NK, int D, bool TRAJ, bool RT = false>
 __device__ __forceinline__ int lane_mismatch(const ATile<NM, NK> &A, const DevProblem &pb, int lane,
                                              const uint32_t *obs_r, const uint32_t *obs_w,
@@ -416,14 +418,15 @@ __device__ __forceinline__ int lane_mismatch(const ATile<NM, NK> &A, const DevPr
       }
     };
     observe(B0, 0);
+    const int t_end = TRAJ ? pb.T : uniform(pb.obs_t[pb.K - 1]);
     int t = 1;
-    for (; t + 1 <= pb.T; t += 2) {
+    for (; t + 1 <= t_end; t += 2) {
       time_step<NM, NK, D, RT>(A, B0, B1, CM, nm, nk);
       observe(B1, t);
       time_step<NM, NK, D, RT>(A, B1, B0, CM, nm, nk);
       observe(B0, t + 1);
     }
-    if (t <= pb.T) {
+    if (t <= t_end) {
       time_step<NM, NK, D, RT>(A, B0, B1, CM, nm, nk);
       observe(B1, t);
     }

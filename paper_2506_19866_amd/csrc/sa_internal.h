@@ -5,14 +5,13 @@
 // -----------------------------------------------------------------
 // One wavefront owns one chain.  The synchronous update of all nodes under 16
 // conditions at once is one product per time step,
-//     X[row(i)][c] = sum_j A[row(i)][col(j)] * S[col(j)][c] = h_i - 1,
+//     X[row(i)][c] = sum_j A[row(i)][col(j)] * S[col(j)][c] = 2 (h_i - 1),
 // where A holds the chain's edge values a_ji in {-1, 0, 1} (and -theta_i - 1
 // in {-3, -2, -1} in the column of a constant "bias" input fixed at 1), and S
-// the states, one column per condition.  States are held as 2s (codes 0x0,
-// 0x4, 0x6 of 0, 2.0, 4.0) and the B operand carries the scale 2^-1, so both
-// operands are exact fp4 (e2m1) codes and the product runs as
-// v_mfma_scale_f32_16x16x128_f8f6f4 tiles with float32 results that are exact
-// small integers: A is the 16x128 A operand of m-tile mt and k-fragment kf,
+// the states, one column per condition, held as 2s (codes 0x0, 0x4, 0x6 of
+// 0, 2.0, 4.0).  Both operands are exact fp4 (e2m1) codes and the product
+// runs as unscaled v_mfma_f32_16x16x128_f8f6f4 tiles with float32 results
+// that are exact small integers: A is the 16x128 A operand of m-tile mt and k-fragment kf,
 // S the 128x16 B operand of k-fragment kf.  A state's code is a thermometer
 // code: bit 2 is [s >= 1], bit 1 is [s >= 2].
 //

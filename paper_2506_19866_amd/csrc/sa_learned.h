@@ -103,14 +103,15 @@ __device__ __forceinline__ int refresh_simulation(const ATile<NM, NK> &A, const 
       tnext = k < pb.K ? uniform(pb.obs_t[k]) : -1;
     };
     observe(B0, 0);
+    const int t_end = uniform(pb.obs_t[pb.K - 1]);  // later states enter no aggregate
     int t = 1;
-    for (; t + 1 <= pb.T; t += 2) {
+    for (; t + 1 <= t_end; t += 2) {
       time_step<NM, NK, D, false>(A, B0, B1, CM, NM, NK);
       observe(B1, t);
       time_step<NM, NK, D, false>(A, B1, B0, CM, NM, NK);
       observe(B0, t + 1);
     }
-    if (t <= pb.T) {
+    if (t <= t_end) {
       time_step<NM, NK, D, false>(A, B0, B1, CM, NM, NK);
       observe(B1, t);
     }

@@ -98,6 +98,25 @@ def test_observation_at_time_zero_and_penalty():
     assert np.array_equal(_gpu_costs(prob, xs), OracleProblem(prob).cost_batch(xs))
 
 
+@pytest.mark.parametrize("d", [1, 2])
+def test_horizon_beyond_last_observation(d):
+    """States after the last observed time enter no cost (the kernels stop
+    simulating there); trajectories still cover the whole horizon."""
+    prob, _ = random_problem(5100 + d, n_nodes=40, n_edges=140, n_cond=10, n_steps=12, n_times=3, n_obs=12,
+                             noise=0.1, clamps=(1, 2), step_size=d)
+    prob = dict(prob, n_steps=19)
+    rng = np.random.default_rng(51 + d)
+    xs = np.concatenate([synth.random_params(rng, 40, prob["n_edges"], prob["n_nodes"]),
+                         synth.feasible_params(rng, 8, prob["row_ptr"], prob["src"])])
+    o = OracleProblem(prob)
+    assert np.array_equal(_gpu_costs(prob, xs), o.cost_batch(xs))
+    traj = _sa().Problem(prob).simulate(_dev(xs[:4])).cpu().numpy()
+    assert traj.shape[2] == 20
+    for i in range(4):
+        assert np.array_equal(traj[i], o.simulate(xs[i])), i
+    _compare_runs(prob, xs[40:], 13, T0=1.3, rho=0.8, n_stages=2, L=40)
+
+
 @pytest.mark.parametrize("name", ["c1", "c2", "c3"])
 def test_workload_costs(name):
     w = synth.load_workload(name)
