@@ -89,8 +89,8 @@ __device__ __forceinline__ void run_chain(const DevProblem &pb, const ChainJob &
       // structural constraints (§2.5.3) from the per-node counts
       int vc = vcur, src = 0, dst = 0, on_new = 0, ip_new = 0;
       if (is_edge) {
-        src = pb.edge_src[p];
-        dst = pb.edge_dst[p];
+        src = load_uniform(pb.edge_src, p);
+        dst = load_uniform(pb.edge_dst, p);
         const int on = uniform((int)outnz[src]), ip = uniform((int)inplus[dst]);
         on_new = on + (nv != 0) - (old != 0);
         ip_new = ip + (nv == 1) - (old == 1);
@@ -112,7 +112,7 @@ __device__ __forceinline__ void run_chain(const DevProblem &pb, const ChainJob &
                 pb.lambda * vc;
       const int delta = ccand - ccur;
       // Metropolis in fixed point: accept iff delta <= 0 or u32 < tau[delta]
-      const bool accept = feasible && (delta <= 0 || (delta <= job.dcap && r2 < job.tau[delta]));
+      const bool accept = feasible && (delta <= 0 || (delta <= job.dcap && r2 < load_uniform(job.tau, delta)));
       patch_a(A, reg, accept ? 0u : mask, param_bits(p, E, old));
       if constexpr (Hooks::kEnabled)
         hk->record(job.g0 + (uint64_t)(it0 + j), p, old, nv, feasible, delta, accept, source, outnz, inplus, lane);

@@ -45,6 +45,16 @@ __device__ __forceinline__ int wave_sum(int v) {
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Element i (wave-uniform) of a table that nothing writes while a kernel
+// runs, loaded through the scalar unit: the constant address space tells the
+// compiler that the memory does not change, so the load becomes s_load
+// instead of a vector load and a lane read.
+template <typename T>
+__device__ __forceinline__ T load_uniform(const T *table, int i) {
+  typedef const __attribute__((address_space(4))) T *ConstPtr;
+  return ((ConstPtr)table)[i];
+}
+
 // ---------------------------------------------------------------------------
 // Philox4x64-10 (Salmon et al., SC'11): ten rounds of two 64x64->128
 // multiplications by the Philox constants, the high halves mixed with the
@@ -193,7 +203,7 @@ __device__ __forceinline__ uint32_t param_bits(int p, int E, int v) {
 template <int NK>
 __device__ __forceinline__ void param_patch_args(const DevProblem &pb, int lane, int p, int v, int &reg,
                                                  uint32_t &mask, uint32_t &bits) {
-  const uint32_t pos = pb.param_pos[p];
+  const uint32_t pos = load_uniform(pb.param_pos, p);
   const int mt = (int)((pos >> 8) & 15u), kf = (int)((pos >> 12) & 3u), dw = (int)((pos >> 14) & 3u);
   reg = (mt * NK + kf) * 4 + dw;
   mask = (lane == (int)(pos & 63u)) ? (0xfu << (4 * ((pos >> 16) & 7u))) : 0u;
@@ -408,17 +418,17 @@ __device__ __forceinline__ int lane_mismatch(const ATile<NM, NK> &A, const DevPr
     const uint32_t *rbase = obs_r + (size_t)cg * pb.K * pb.nd * kWave;
     const uint32_t *wbase = obs_w + (size_t)cg * pb.K * pb.nd * kWave;
     int k = 0;
-    int tnext = uniform(pb.obs_t[0]);
+    int tnext = load_uniform(pb.obs_t, 0);
     auto observe = [&](const v4i (&B)[NK], int t) SA_INLINE {
       if (TRAJ) write_states<NK>(B, pb, lane, c, t, traj);
       if (t == tnext) {
         total += score<NK>(B, rbase + (size_t)k * pb.nd * kWave, wbase + (size_t)k * pb.nd * kWave, pb.nd, lane);
         ++k;
-        tnext = k < pb.K ? uniform(pb.obs_t[k]) : -1;
+        tnext = k < pb.K ? load_uniform(pb.obs_t, k) : -1;
       }
     };
     observe(B0, 0);
-    const int t_end = TRAJ ? pb.T : uniform(pb.obs_t[pb.K - 1]);
+    const int t_end = TRAJ ? pb.T : load_uniform(pb.obs_t, pb.K - 1);
     int t = 1;
     for (; t + 1 <= t_end; t += 2) {
       time_step<NM, NK, D, RT>(A, B0, B1, CM, nm, nk);

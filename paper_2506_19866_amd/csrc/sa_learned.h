@@ -84,7 +84,7 @@ __device__ __forceinline__ int refresh_simulation(const ATile<NM, NK> &A, const 
       acc[2 * q4] += v & 0x0f0f0f0fu;
       acc[2 * q4 + 1] += (v >> 4) & 0x0f0f0f0fu;
     };
-    int k = 0, tnext = uniform(pb.obs_t[0]);
+    int k = 0, tnext = load_uniform(pb.obs_t, 0);
     auto observe = [&](const v4i (&B)[NK], int t) SA_INLINE {
       if (t != tnext) return;
 #pragma unroll
@@ -100,10 +100,10 @@ __device__ __forceinline__ int refresh_simulation(const ATile<NM, NK> &A, const 
         }
       }
       ++k;
-      tnext = k < pb.K ? uniform(pb.obs_t[k]) : -1;
+      tnext = k < pb.K ? load_uniform(pb.obs_t, k) : -1;
     };
     observe(B0, 0);
-    const int t_end = uniform(pb.obs_t[pb.K - 1]);  // later states enter no aggregate
+    const int t_end = load_uniform(pb.obs_t, pb.K - 1);  // later states enter no aggregate
     int t = 1;
     for (; t + 1 <= t_end; t += 2) {
       time_step<NM, NK, D, false>(A, B0, B1, CM, NM, NK);
