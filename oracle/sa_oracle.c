@@ -270,6 +270,9 @@ typedef struct {
   int32_t steps_per_stage;
   int32_t n_threads;
   int64_t first_chain;  /* Philox chain id of chain 0 (to recompute any subset of a larger run) */
+  int64_t group_size;   /* island restart: 0 (or >= n_chains) restarts every chain from the global
+                           best (Table 1); G restarts each group of G consecutive chains from the
+                           best of that group (the grouped reduction suggested in §4) */
 } ora_run_args;
 
 typedef struct {
@@ -328,7 +331,8 @@ static void *run_chains_of_stage(void *arg) {
 
 /* Returns 0 on success, -1 if a starting vector breaks a constraint in hard
  * mode.  Outputs (any may be NULL):
- *   x_out[P], cost_out, winner_out: global best after the last stage;
+ *   x_out[P], cost_out, winner_out: global best of the last stage (lowest
+ *   chain id on ties), before the restart;
  *   stage_best[S], stage_winner[S], stage_accepted[S], stage_uphill[S],
  *   stage_neutral[S], stage_infeasible[S]: per stage, before the restart;
  *   chain_best[n_chains], chain_xbest[n_chains*P]: every chain's best after
@@ -356,6 +360,10 @@ int ora_run(const ora_problem *p, const ora_run_args *args, const int8_t *x0,
   ora_worker *workers = (ora_worker *)calloc((size_t)n_threads, sizeof(ora_worker));
   pthread_t *tids = (pthread_t *)calloc((size_t)n_threads, sizeof(pthread_t));
   int64_t winner = 0;
+  const int64_t G = args->group_size > 0 && args->group_size < n ? args->group_size : n;
+  int8_t *xw = (int8_t *)malloc((size_t)P);
+  int8_t *x_glob = (int8_t *)malloc((size_t)P);
+  int64_t c_glob = 0;
   for (int32_t s = 0; s < args->n_stages && status == 0; ++s) {
     int64_t k = (int64_t)args->first_stage + s;
     double T = ora_stage_temperature(args->T0, args->rho, k);
@@ -378,7 +386,7 @@ int ora_run(const ora_problem *p, const ora_run_args *args, const int8_t *x0,
       neu += workers[t].neutral; inf += workers[t].infeasible;
     }
     /* Table 1, serial part: global minimum over all chains (lowest chain id
-     * on ties), then every chain restarts from that vector. */
+     * on ties); it is the stage's result. */
     winner = 0;
     for (int64_t c = 1; c < n; ++c)
       if (c_best[c] < c_best[winner]) winner = c;
@@ -392,21 +400,31 @@ int ora_run(const ora_problem *p, const ora_run_args *args, const int8_t *x0,
       if (chain_best) memcpy(chain_best, c_best, sizeof(int64_t) * (size_t)n);
       if (chain_xbest) memcpy(chain_xbest, x_best, (size_t)(n * P));
     }
-    int64_t cw = c_best[winner];
-    int8_t *xw = (int8_t *)malloc((size_t)P);
-    memcpy(xw, x_best + winner * P, (size_t)P);
-    for (int64_t c = 0; c < n; ++c) {
-      memcpy(x_cur + c * P, xw, (size_t)P);
-      memcpy(x_best + c * P, xw, (size_t)P);
-      c_cur[c] = c_best[c] = cw;
+    memcpy(x_glob, x_best + winner * P, (size_t)P);
+    c_glob = c_best[winner];
+    /* Restart: every chain from its group's best (lowest chain id on ties
+     * within the group); one group of all chains is Table 1's global restart. */
+    for (int64_t g0 = 0; g0 < n; g0 += G) {
+      const int64_t g1 = g0 + G < n ? g0 + G : n;
+      int64_t gw = g0;
+      for (int64_t c = g0 + 1; c < g1; ++c)
+        if (c_best[c] < c_best[gw]) gw = c;
+      const int64_t cw = c_best[gw];
+      memcpy(xw, x_best + gw * P, (size_t)P);
+      for (int64_t c = g0; c < g1; ++c) {
+        memcpy(x_cur + c * P, xw, (size_t)P);
+        memcpy(x_best + c * P, xw, (size_t)P);
+        c_cur[c] = c_best[c] = cw;
+      }
     }
-    free(xw);
   }
+  free(xw);
   if (status == 0) {
-    if (x_out) memcpy(x_out, x_best, (size_t)P);
-    if (cost_out) *cost_out = c_best[0];
+    if (x_out) memcpy(x_out, args->n_stages > 0 ? x_glob : x_best, (size_t)P);
+    if (cost_out) *cost_out = args->n_stages > 0 ? c_glob : c_best[0];
     if (winner_out) *winner_out = winner;
   }
+  free(x_glob);
   free(workers); free(tids);
   free(x_cur); free(x_best); free(c_cur); free(c_best);
   return status;

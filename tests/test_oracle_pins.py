@@ -409,6 +409,52 @@ def test_resume_is_bit_identical():
     assert np.array_equal(full["x"], tail["x"])
 
 
+@pytest.mark.parametrize("G", [0, 12, 40])
+def test_one_group_of_all_chains_is_the_global_restart(G):
+    """Island restart: a group that holds every chain is Table 1's restart."""
+    w = synth.load_workload("c1")
+    x0 = synth.start_vectors("c1", w, 12)
+    ref = _run(w, x0)
+    got = _run(w, x0, group_size=G)
+    for k in ref:
+        assert np.array_equal(np.asarray(ref[k]), np.asarray(got[k])), k
+
+
+@pytest.mark.parametrize("G", [1, 4, 5])
+def test_groups_evolve_as_separate_runs(G):
+    """Each group of G consecutive chains (the last one ragged) restarts from
+    its own best, so it evolves exactly as a separate Table 1 run over those
+    chains with the same Philox chain ids; the stage records of the grouped
+    run are the minimum (lowest chain id on ties) and the sums over groups."""
+    w = synth.load_workload("c1")
+    n = 11
+    x0 = synth.start_vectors("c1", w, n)
+    got = _run(w, x0, group_size=G, n_stages=5)
+    S = 5
+    best = np.full(S, np.iinfo(np.int64).max)
+    win = np.zeros(S, dtype=np.int64)
+    acc = np.zeros(S, dtype=np.uint64)
+    inf = np.zeros(S, dtype=np.uint64)
+    gbest, gx = None, None
+    for g0 in range(0, n, G):
+        g1 = min(g0 + G, n)
+        sub = _run(w, x0[g0:g1], first_chain=g0, n_stages=5)
+        assert np.array_equal(got["chain_best"][g0:g1], sub["chain_best"]), g0
+        assert np.array_equal(got["chain_xbest"][g0:g1], sub["chain_xbest"]), g0
+        better = sub["stage_best"] < best
+        best = np.where(better, sub["stage_best"], best)
+        win = np.where(better, sub["stage_winner"] + g0, win)
+        acc += sub["stage_accepted"]
+        inf += sub["stage_infeasible"]
+        if gbest is None or sub["cost"] < gbest:
+            gbest, gx = sub["cost"], sub["x"]
+    assert np.array_equal(got["stage_best"], best)
+    assert np.array_equal(got["stage_winner"], win)
+    assert np.array_equal(got["stage_accepted"], acc)
+    assert np.array_equal(got["stage_infeasible"], inf)
+    assert got["cost"] == gbest and np.array_equal(got["x"], gx)
+
+
 def test_greedy_limit_never_goes_uphill():
     w = synth.load_workload("c1")
     x0 = synth.start_vectors("c1", w, 4)
