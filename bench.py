@@ -298,6 +298,42 @@ def bench_learned_cost(args) -> int:
     return 0
 
 
+def bench_sweep(args) -> int:
+    """Chain-count sweep over the thread counts of the paper's Table 2 (32,
+    256, 1024, 10240, 102400) on the full c3 schedule, with Table 1's global
+    restart and with the island restart in groups of --group chains (the
+    reduction suggested in §4).  One JSON line per configuration: throughput,
+    stage-kernel time of the schedule, final best cost and the stage-kernel
+    time until the global best first reaches each target cost."""
+    import torch
+    from paper_2506_19866_amd import sa, synth
+    prob, s = synth.load_workload("c3"), synth.bench_schedule("c3")
+    L, S = s["steps_per_stage"], s["n_stages"]
+    P = sa.Problem(prob)
+    for n in args.chain_list:
+        x0 = torch.from_numpy(synth.start_vectors("c3", prob, n)).cuda()
+        for group in (0, args.group):
+            if group and group >= n:
+                continue
+            run = sa.Run(P, x0, seed=s["seed"], T0=s["T0"], rho=s["rho"], n_stages=S, steps_per_stage=L,
+                         record_times=True, group_size=group)
+            ms = run.stage_times_ms()
+            best = run.stats()["best_cost"]
+            run.close()
+            t = np.cumsum(ms) * 1e-3
+            reach = {}
+            for target in args.targets:
+                hit = np.nonzero(best <= target)[0]
+                reach[str(target)] = float(t[hit[0]]) if hit.size else None
+            out = {"chains": n, "restart": f"island {group}" if group else "global", "stages": S,
+                   "chain_steps_per_s": n * L * S / float(t[-1]), "schedule_stage_kernel_s": float(t[-1]),
+                   "final_best": int(best[-1]), "time_to_target_s": reach}
+            log(f"[sweep] {out}")
+            print(json.dumps(out), flush=True)
+        del x0
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -307,9 +343,13 @@ def main() -> int:
                     help="c4 = the batched workload (256 uneven networks, one persistent launch per stage)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--mode", default="throughput", choices=["throughput", "learned", "learned-cost"],
+    ap.add_argument("--mode", default="throughput", choices=["throughput", "learned", "learned-cost", "sweep"],
                     help="learned: train the proposal network on c2 traces and compare time-to-target on c3; "
-                         "learned-cost: per-stage cost of the learned kernel against the plain one on c3")
+                         "learned-cost: per-stage cost of the learned kernel against the plain one on c3; "
+                         "sweep: chain counts of the paper's Table 2 with global and island restarts on c3")
+    ap.add_argument("--chain-list", type=int, nargs="+", default=[32, 256, 1024, 10240, 102400])
+    ap.add_argument("--group", type=int, default=32, help="sweep: chains per island restart group")
+    ap.add_argument("--targets", type=int, nargs="+", default=[1400, 1350, 1300])
     ap.add_argument("--refresh-list", type=int, nargs="+", default=[16, 64, 256])
     ap.add_argument("--trace-rows", type=int, default=1 << 20)
     ap.add_argument("--trace-workload", default="c2", choices=["c1", "c2", "c3"])
@@ -344,6 +384,8 @@ def main() -> int:
         return bench_learned(args)
     if args.mode == "learned-cost":
         return bench_learned_cost(args)
+    if args.mode == "sweep":
+        return bench_sweep(args)
 
     name = args.workload
     if name == "c4":

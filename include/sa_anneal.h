@@ -156,6 +156,12 @@ typedef struct {
                                 multiple of trace_every are recorded, in slot (g - g_first) / trace_every
                                 where g_first is the run's first such g; slots beyond the capacity are
                                 dropped.  Features use the aggregates of the chain's last refresh. */
+  int64_t group_size;        /* >= 0.  Island restart (the reduction within groups of chains suggested
+                                in §4): with 0 < group_size < n_chains, at every stage boundary each group
+                                of group_size consecutive chains (the last one may be shorter) restarts
+                                from its own best chain (lowest chain id on ties) instead of the global
+                                best; 0 or >= n_chains is Table 1's global restart.  Stage statistics and
+                                sa_best still report the global best.  Plain proposals only. */
 } sa_run_desc;
 
 enum { SA_KERNEL_AUTO = 0, SA_KERNEL_PERSISTENT = 1 };

@@ -81,6 +81,7 @@ struct sa_run {
   std::vector<size_t> tau_off;
   std::vector<int32_t> dcap;
   int32_t launched = 0;
+  int64_t group = 0;               // chains per restart group (0: Table 1's global restart)
   hipStream_t stream = nullptr;
   std::vector<hipEvent_t> ev_start, ev_stop;  // per stage, when record_times is set
   std::vector<hipGraphExec_t> graphs;
@@ -537,6 +538,7 @@ static int enqueue_stage(sa_run *r, int32_t st, hipStream_t stream) {
     a.tau = r->tau + r->tau_off[st];
     a.x_start = first ? r->x0 : r->xwin;
     a.x_start_stride = first ? pb.P : 0;
+    a.group = first ? 0 : r->group;
     a.xbest = r->xbest;
     a.cbest = r->cbest;
     a.cstats = r->cstats;
@@ -565,6 +567,7 @@ static int enqueue_stage(sa_run *r, int32_t st, hipStream_t stream) {
       a.tau = r->tau + r->tau_off[st];
       a.x_start = first ? r->x0 : r->xwin;
       a.first = first;
+      a.group = r->group;
       a.x_off = r->x_off_dev;
       a.w_off = r->w_off_dev;
       a.xbest = r->xbest;
@@ -580,6 +583,7 @@ static int enqueue_stage(sa_run *r, int32_t st, hipStream_t stream) {
   sa::BatchReduceArgs ra{};
   ra.n_probs = np;
   ra.n_chains = r->n;
+  ra.group = r->group;
   ra.probs = r->probs_dev;
   ra.x_off = r->x_off_dev;
   ra.w_off = r->w_off_dev;
@@ -652,6 +656,7 @@ extern "C" int sa_run_create(sa_problem *const *probs, int32_t n_probs, const sa
       desc->chains_per_block != 4 && desc->chains_per_block != 8)
     return fail(SA_ERR_ARG, "chains_per_block must be 0 (autotune), 1, 2, 4 or 8");
   if (desc->record_times && desc->use_graph) return fail(SA_ERR_ARG, "record_times and use_graph exclude each other");
+  if (desc->group_size < 0) return fail(SA_ERR_ARG, "group_size must be >= 0");
   const bool learned = desc->proposal == SA_PROPOSAL_LEARNED, traced = desc->trace_dev != nullptr;
   if (desc->proposal != SA_PROPOSAL_PLAIN && !learned) return fail(SA_ERR_ARG, "unknown proposal %d", desc->proposal);
   if (learned && !desc->model) return fail(SA_ERR_ARG, "the learned proposal needs a model");
@@ -663,6 +668,8 @@ extern "C" int sa_run_create(sa_problem *const *probs, int32_t n_probs, const sa
   if (learned || traced) {
     if (n_probs != 1 || desc->kernel != SA_KERNEL_AUTO)
       return fail(SA_ERR_UNSUPPORTED, "the learned proposal and the trace run one problem on the specialised kernel");
+    if (desc->group_size > 0 && desc->group_size < desc->n_chains)
+      return fail(SA_ERR_UNSUPPORTED, "the learned proposal and the trace restart every chain from the global best");
     const sa::DevProblem &dp = probs[0]->dev;
     if (dp.nm > sa::kLearnedMaxTilesM)
       return fail(SA_ERR_UNSUPPORTED, "learned proposal / trace: %d nodes (at most 127)", dp.N);
@@ -690,13 +697,15 @@ extern "C" int sa_run_create(sa_problem *const *probs, int32_t n_probs, const sa
   r->n = n;
   r->persistent = persistent;
   r->stream = s;
+  r->group = desc->group_size > 0 && desc->group_size < n ? desc->group_size : 0;
+  const int64_t n_groups = r->group ? (n + r->group - 1) / r->group : 1;
   int64_t xo = 0, wo = 0;
   int32_t max_cost = 0;
   for (int i = 0; i < n_probs; ++i) {
     r->x_off.push_back(xo);
     r->w_off.push_back(wo);
     xo += n * probs[i]->dev.P;
-    wo += probs[i]->dev.P;
+    wo += n_groups * probs[i]->dev.P;
     max_cost = std::max(max_cost, probs[i]->info.max_cost);
   }
   if (learned || traced) {
@@ -919,9 +928,11 @@ extern "C" int sa_best(sa_run *r, int32_t prob, int8_t *x_host, int32_t *cost, i
   sa::StageRecord rec;
   SA_HIP(hipMemcpy(&rec, r->rec + (size_t)(r->launched - 1) * np + prob, sizeof(rec), hipMemcpyDeviceToHost),
          "copy record");
+  // the global winner is also the winner of its restart group
+  const int64_t P = r->probs[prob]->dev.P;
+  const int64_t slot = r->group ? rec.winner / r->group : 0;
   if (x_host)
-    SA_HIP(hipMemcpy(x_host, r->xwin + r->w_off[prob], (size_t)r->probs[prob]->dev.P, hipMemcpyDeviceToHost),
-           "copy best");
+    SA_HIP(hipMemcpy(x_host, r->xwin + r->w_off[prob] + slot * P, (size_t)P, hipMemcpyDeviceToHost), "copy best");
   if (cost) *cost = rec.best_cost;
   if (winner) *winner = rec.winner;
   return SA_OK;

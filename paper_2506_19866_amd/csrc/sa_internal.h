@@ -77,8 +77,9 @@ struct StageArgs {
   int32_t L;              // steps per stage
   int32_t dcap;           // largest uphill move with a non-zero threshold
   const uint32_t *tau;    // [dcap+1] thresholds of this stage (entry 0 unused)
-  const int8_t *x_start;  // first stage: [n_chains*P]; later: winner [P]
-  int64_t x_start_stride; // P or 0
+  const int8_t *x_start;  // first stage: [n_chains*P]; later: winner [P], or one per group [n_groups*P]
+  int64_t x_start_stride; // P (first stage) or 0
+  int64_t group;          // later stages: chains per restart group (chain c starts from winner c / group), 0: one winner
   int8_t *xbest;          // [n_chains*P] out
   int32_t *cbest;         // [n_chains] out
   uint32_t *cstats;       // [n_chains*4] out: accepted, uphill, neutral, infeasible
@@ -106,8 +107,9 @@ struct BatchArgs {
   uint64_t seed;
   int32_t stage, L, dcap;
   const uint32_t *tau;        // [dcap+1]
-  const int8_t *x_start;      // first stage: x0 at x_off; later: winners at w_off
+  const int8_t *x_start;      // first stage: x0 at x_off; later: winners at w_off (one per restart group)
   int32_t first;
+  int64_t group;              // chains per restart group, 0: one group
   const int64_t *x_off;       // [n_probs]: byte offset of the network's chain vectors
   const int64_t *w_off;       // [n_probs]: byte offset of the network's winner vector
   int8_t *xbest;              // at x_off
@@ -117,10 +119,12 @@ struct BatchArgs {
 
 // Table 1's serial part for every network of a run (one block per network):
 // winner, its vector copied for the next stage, statistics summed; also resets
-// the work queue of the persistent kernel.
+// the work queue of the persistent kernel.  With restart groups the winner is
+// only recorded, and the group kernel copies every group's own winner.
 struct BatchReduceArgs {
   int32_t n_probs;
   int64_t n_chains;
+  int64_t group;              // chains per restart group, 0: one group
   const DevProblem *probs;
   const int64_t *x_off, *w_off;
   const int32_t *cbest;

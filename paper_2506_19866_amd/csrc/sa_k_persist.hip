@@ -33,7 +33,8 @@ __global__ __launch_bounds__(512) void persistent_kernel(BatchArgs a) {
     if (wv < a.waves && chain < a.n_chains) {
       const int64_t gc = (int64_t)net * a.n_chains + chain;
       ChainJob job;
-      job.x_start = a.first ? a.x_start + a.x_off[net] + chain * pb.P : a.x_start + a.w_off[net];
+      job.x_start = a.first ? a.x_start + a.x_off[net] + chain * pb.P
+                            : a.x_start + a.w_off[net] + (a.group ? chain / a.group : 0) * pb.P;
       job.xbest = a.xbest + a.x_off[net] + chain * pb.P;
       job.cbest = a.cbest + gc;
       job.stats = a.cstats + gc * 4;
@@ -95,10 +96,40 @@ __global__ __launch_bounds__(256) void batch_reduce_kernel(BatchReduceArgs ra) {
     if (net == 0 && ra.queue)  // one work counter per (size class, step size) launch
       for (int q = 0; q < kPersistentQueues; ++q) ra.queue[q] = 0u;
   }
+  if (ra.group) return;  // every restart group copies its own winner (group_restart_kernel)
   const int P = ra.probs[net].P;
   const int8_t *from = ra.xbest + ra.x_off[net] + winner * P;
   int8_t *to = ra.xwin + ra.w_off[net];
   for (int i = tid; i < P; i += 256) to[i] = from[i];
+}
+
+// Island restart: one wavefront per restart group of ra.group consecutive
+// chains (the last group of a network may be shorter): the group's best
+// chain (lowest chain id on ties) is copied to the group's winner slot, from
+// which every chain of the group starts the next stage.
+__global__ __launch_bounds__(256) void group_restart_kernel(BatchReduceArgs ra, int64_t groups_per_net) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t gid = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  if (gid >= (int64_t)ra.n_probs * groups_per_net) return;
+  const int net = (int)(gid / groups_per_net);
+  const int64_t g = gid % groups_per_net;
+  const int64_t c0 = g * ra.group, c1 = min(c0 + ra.group, ra.n_chains);
+  const int64_t base = (int64_t)net * ra.n_chains;
+  unsigned long long best = ~0ull;
+  for (int64_t c = c0 + lane; c < c1; c += kWave) {
+    const unsigned long long key = ((unsigned long long)(uint32_t)ra.cbest[base + c] << 32) | (unsigned long long)c;
+    best = key < best ? key : best;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long o = __shfl_xor(best, off, kWave);
+    best = o < best ? o : best;
+  }
+  const int64_t winner = (int64_t)(best & 0xffffffffull);
+  const int P = ra.probs[net].P;
+  const int8_t *from = ra.xbest + ra.x_off[net] + winner * P;
+  int8_t *to = ra.xwin + ra.w_off[net] + g * P;
+  for (int i = lane; i < P; i += kWave) to[i] = from[i];
 }
 
 size_t persistent_smem_bytes(const DevProblem &pb, int waves) {
@@ -147,6 +178,11 @@ int launch_persistent(const BatchArgs &a, int cls, int d, int grid, size_t smem,
 
 int launch_batch_reduce(const BatchReduceArgs &ra, void *stream) {
   batch_reduce_kernel<<<ra.n_probs, 256, 0, (hipStream_t)stream>>>(ra);
+  if (ra.group > 0) {
+    const int64_t groups_per_net = (ra.n_chains + ra.group - 1) / ra.group;
+    group_restart_kernel<<<grid_for((int64_t)ra.n_probs * groups_per_net), 256, 0, (hipStream_t)stream>>>(
+        ra, groups_per_net);
+  }
   return (int)hipGetLastError();
 }
 

@@ -23,7 +23,7 @@ __global__ __launch_bounds__(256) void stage_kernel(DevProblem pb, StageArgs sa)
   const int64_t chain = (int64_t)blockIdx.x * kWavesPerBlock + wv;
   if (chain >= sa.n_chains) return;
   ChainJob job;
-  job.x_start = sa.x_start + chain * sa.x_start_stride;
+  job.x_start = sa.x_start + (sa.group ? (chain / sa.group) * pb.P : chain * sa.x_start_stride);
   job.xbest = sa.xbest + chain * pb.P;
   job.cbest = sa.cbest + chain;
   job.stats = sa.cstats + chain * 4;

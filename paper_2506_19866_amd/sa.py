@@ -68,6 +68,7 @@ class _RunDesc(C.Structure):
         ("use_graph", C.c_int32),
         ("proposal", C.c_int32), ("refresh_every", C.c_int32), ("model", C.c_void_p), ("eps_plain", C.c_double),
         ("trace_dev", C.c_void_p), ("trace_capacity", C.c_int64), ("trace_every", C.c_int32),
+        ("group_size", C.c_int64),
     ]
 
 
@@ -231,12 +232,13 @@ class Run:
                  steps_per_stage: int, first_stage: int = 0, stream=None, launch: bool = True,
                  record_times: bool = False, kernel: int = SA_KERNEL_AUTO, chains_per_block: int = 0,
                  use_graph: bool = False, model: "Mlp | None" = None, refresh_every: int = 16,
-                 eps_plain: float = 0.1, trace=None, trace_every: int = 1):
+                 eps_plain: float = 0.1, trace=None, trace_every: int = 1, group_size: int = 0):
         """problems: a Problem or a list of them; x0: int8 CUDA tensor [n_chains, P]
         for one problem, or a list (one [n_chains, P_p] tensor per problem).
         model: learned proposal with this network; trace: uint8 CUDA tensor
         [n_chains, capacity * 80] receiving sa_trace_record rows (decode with
-        decode_trace)."""
+        decode_trace).  group_size G > 0: island restart, each group of G
+        consecutive chains restarts from its own best (0: the global best)."""
         import torch
         if isinstance(problems, Problem):
             problems, x0 = [problems], [x0]
@@ -261,7 +263,7 @@ class Run:
                      int(steps_per_stage), 1 if record_times else 0, int(kernel), int(chains_per_block),
                      1 if use_graph else 0, SA_PROPOSAL_LEARNED if model is not None else SA_PROPOSAL_PLAIN,
                      int(refresh_every), model.handle if model is not None else None, float(eps_plain),
-                     trace_ptr, int(cap), int(trace_every))
+                     trace_ptr, int(cap), int(trace_every), int(group_size))
         probs = (C.c_void_p * len(self.problems))(*[p.handle for p in self.problems])
         h = C.c_void_p()
         _check(lib().sa_run_create(probs, len(self.problems), C.byref(d), C.c_void_p(self._x0.data_ptr()),

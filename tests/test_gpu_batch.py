@@ -27,11 +27,11 @@ def _dev(x):
     return torch.from_numpy(np.ascontiguousarray(x, dtype=np.int8)).cuda()
 
 
-def _check_against_oracle(run, probs, x0s, seed, T0, rho, S, L, first_stage=0, nets=None):
+def _check_against_oracle(run, probs, x0s, seed, T0, rho, S, L, first_stage=0, nets=None, group_size=0):
     for p, (prob, x0) in enumerate(zip(probs, x0s)):
         net = p if nets is None else nets[p]
         ref = OracleProblem(prob).run(x0, seed=seed, T0=T0, rho=rho, n_stages=S, steps_per_stage=L,
-                                      first_stage=first_stage, net=net, n_threads=8)
+                                      first_stage=first_stage, net=net, n_threads=8, group_size=group_size)
         st = run.stats(p)
         x, cost, winner = run.best(p)
         cb, cx = run.chain_best(p)
@@ -83,6 +83,20 @@ def test_uneven_batch_matches_oracle_per_network(use_graph):
     run = sa.Run(P, [_dev(x) for x in x0s], seed=seed, T0=2.0, rho=0.8, n_stages=S, steps_per_stage=L,
                  use_graph=use_graph, chains_per_block=0)
     _check_against_oracle(run, probs, x0s, seed, 2.0, 0.8, S, L)
+
+
+def test_uneven_batch_island_restart():
+    """Island restart in the persistent kernel: groups of 3 of 10 chains per
+    network (the last group is one chain), every network against the oracle."""
+    sa = _sa()
+    probs = _uneven_subset()[:5]
+    n = 10
+    x0s = [synth.feasible_params(np.random.default_rng(30 + i), n, p["row_ptr"], p["src"]) for i, p in enumerate(probs)]
+    P = [sa.Problem(p) for p in probs]
+    S, L, seed = 3, 40, 17
+    run = sa.Run(P, [_dev(x) for x in x0s], seed=seed, T0=2.0, rho=0.8, n_stages=S, steps_per_stage=L,
+                 use_graph=True, chains_per_block=2, group_size=3)
+    _check_against_oracle(run, probs, x0s, seed, 2.0, 0.8, S, L, group_size=3)
 
 
 def test_batch_independent_of_tiling_and_launch_split():

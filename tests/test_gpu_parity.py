@@ -141,14 +141,14 @@ def test_empty_batch_is_a_noop():
 # ---------------------------------------------------------------------------
 # annealing runs (Table 1): bit-identical to the oracle
 # ---------------------------------------------------------------------------
-def _compare_runs(prob, x0, name_seed, *, T0, rho, n_stages, L, first_stage=0, hard=1):
+def _compare_runs(prob, x0, name_seed, *, T0, rho, n_stages, L, first_stage=0, hard=1, group_size=0, **kw):
     o = OracleProblem(prob)
     ref = o.run(x0, seed=name_seed, T0=T0, rho=rho, n_stages=n_stages, steps_per_stage=L,
-                first_stage=first_stage, n_threads=8)
+                first_stage=first_stage, n_threads=8, group_size=group_size)
     sa = _sa()
     P = sa.Problem(prob)
     run = sa.Run(P, _dev(x0), seed=name_seed, T0=T0, rho=rho, n_stages=n_stages, steps_per_stage=L,
-                 first_stage=first_stage)
+                 first_stage=first_stage, group_size=group_size, **kw)
     st = run.stats()
     x, cost, winner = run.best()
     cb, cx = run.chain_best()
@@ -184,6 +184,39 @@ def test_run_c3_truncated():
     s = synth.bench_schedule("c3")
     x0 = synth.start_vectors("c3", w, 64)
     _compare_runs(w, x0, s["seed"], T0=s["T0"], rho=s["rho"], n_stages=2, L=40)
+
+
+@pytest.mark.parametrize("G", [1, 5, 8, 21])
+def test_run_island_restart_groups(G):
+    """Island restart (groups of G chains, the last one ragged for G = 5 and 8;
+    G = 21 is every chain) on the specialised kernel, against the oracle."""
+    w = synth.load_workload("c1")
+    s = synth.bench_schedule("c1")
+    x0 = synth.start_vectors("c1", w, 21)
+    _compare_runs(w, x0, 123, T0=s["T0"], rho=s["rho"], n_stages=6, L=60, group_size=G)
+
+
+def test_run_island_restart_c2_graph():
+    """Groups of 32 chains of the c2 workload, stages captured in a hipGraph."""
+    w = synth.load_workload("c2")
+    s = synth.bench_schedule("c2")
+    x0 = synth.start_vectors("c2", w, 100)
+    _compare_runs(w, x0, 77, T0=s["T0"], rho=s["rho"], n_stages=4, L=50, group_size=32, use_graph=True)
+
+
+def test_island_restart_rejections():
+    sa = _sa()
+    w = synth.load_workload("c1")
+    P = sa.Problem(w)
+    x0 = _dev(synth.start_vectors("c1", w, 8))
+    with pytest.raises(sa.SAError) as e:
+        sa.Run(P, x0, seed=1, T0=1.0, rho=0.9, n_stages=1, steps_per_stage=10, group_size=-1, launch=False)
+    assert e.value.code == sa.SA_ERR_ARG
+    trace = torch.zeros((8, 4 * sa.TRACE_RECORD_BYTES), dtype=torch.uint8, device="cuda")
+    with pytest.raises(sa.SAError) as e:
+        sa.Run(P, x0, seed=1, T0=1.0, rho=0.9, n_stages=1, steps_per_stage=10, group_size=4, trace=trace,
+               launch=False)
+    assert e.value.code == sa.SA_ERR_UNSUPPORTED
 
 
 def test_run_resume_mid_schedule_and_penalty_mode():
