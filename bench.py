@@ -186,7 +186,8 @@ def bench_learned(args) -> int:
     traces of plain runs on the HPG-scale workload (about args.trace_rows
     rows), the network trained on them, then plain and learned runs of the
     full c3 schedule for several seeds, compared by the stage-kernel time
-    they need to reach (a) the median final cost of the plain runs and (b)
+    they need to reach (a) a cost that 80% of the plain runs reach (their
+    80th-percentile final cost, so the plain median time is defined) and (b)
     the cost of the generating parameters on the noisy data."""
     import torch
     from paper_2506_19866_amd import proposal, sa, synth
@@ -233,7 +234,7 @@ def bench_learned(args) -> int:
                 f"in {curves[kind][-1][0][-1]:.2f} s of stage kernels, "
                 f"{curves[kind][-1][2]:.5f} of steps accepted improving moves")
     finals = {k: [int(c[1][-1]) for c in v] for k, v in curves.items()}
-    target = int(np.median(finals["plain"]))
+    target = int(np.percentile(finals["plain"], 80, method="lower"))
     tt = {k: [_time_to(c, target) for c in v] for k, v in curves.items()}
     th = {k: [_time_to(c, hidden_cost) for c in v] for k, v in curves.items()}
     total = {k: [float(c[0][-1]) for c in v] for k, v in curves.items()}
@@ -245,7 +246,7 @@ def bench_learned(args) -> int:
         return m if np.isfinite(m) else None
     value = med(tt["learned"])
     out = {
-        "metric": "c3 time to the plain runs' median final cost, learned proposal", "value": value, "unit": "s",
+        "metric": "c3 time to a cost 80% of plain runs reach, learned proposal", "value": value, "unit": "s",
         "n_gpus": 1, "steps": S3, "warmup": 0, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "fp4 simulation, bf16 network",
         "data": f"synthetic (traces from {args.trace_workload} plain runs; evaluation on the stored c3 workload)",
@@ -255,6 +256,7 @@ def bench_learned(args) -> int:
                    "eval_seeds": args.eval_seeds, "epochs": args.epochs},
         "plain_time_to_target_s": tt["plain"], "learned_time_to_target_s": tt["learned"],
         "plain_median_s": med(tt["plain"]), "target_cost": target,
+        "learned_over_plain": (value / med(tt["plain"])) if value is not None and med(tt["plain"]) else None,
         "reached": {k: sum(v is not None for v in vals) for k, vals in tt.items()},
         "final_best_median": {k: float(np.median(v)) for k, v in finals.items()},
         "hidden_params_cost": hidden_cost, "plain_time_to_hidden_s": th["plain"],
