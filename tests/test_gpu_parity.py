@@ -204,6 +204,16 @@ def test_run_island_restart_c2_graph():
     _compare_runs(w, x0, 77, T0=s["T0"], rho=s["rho"], n_stages=4, L=50, group_size=32, use_graph=True)
 
 
+@pytest.mark.parametrize("N,E,C,d,G,first", [(40, 130, 18, 2, 6, 3), (191, 700, 3, 1, 2, 0), (9, 25, 3, 1, 3, 1)])
+def test_run_island_restart_other_layouts(N, E, C, d, G, first):
+    """Island restart with step size 2, the largest layout, and a run resumed
+    mid-schedule (first stage > 0), against the oracle."""
+    prob, _ = random_problem(6000 + N, n_nodes=N, n_edges=E, n_cond=C, n_steps=7, n_times=3,
+                             n_obs=max(2, N // 3), noise=0.1, clamps=(1, 2), step_size=d)
+    x0 = synth.feasible_params(np.random.default_rng(N + 1), 11, prob["row_ptr"], prob["src"])
+    _compare_runs(prob, x0, 29, T0=1.5, rho=0.8, n_stages=3, L=40, first_stage=first, group_size=G)
+
+
 def test_island_restart_rejections():
     sa = _sa()
     w = synth.load_workload("c1")
