@@ -6,7 +6,8 @@ pseudo-experimental data, §2.5.2), so producing them needs the model; this
 script takes that step with the oracle only, once, offline.  Everything else
 comes from the seeded generators in ``paper_2506_19866_amd.synth``.
 
-Recipe per workload (seed = 1000 + config number):
+Recipe per workload (seed = 1000 + config number; priority-model workloads
+q1-q3: 1100 + number):
   1. topology, hidden feasible parameters, conditions, observed times;
   2. oracle trajectories of the hidden parameters under every condition;
   3. observed nodes drawn with weight 1 + (number of state changes over all
@@ -16,7 +17,7 @@ Recipe per workload (seed = 1000 + config number):
      its entries are non-zero, keeping the best of 100 draws otherwise;
   5. noise: a fixed fraction of entries flipped to another level.
 
-Usage:  python oracle/make_workloads.py [c1 c2 c3 c4]
+Usage:  python oracle/make_workloads.py [c1 c2 c3 c4 q1 q2 q3]
 """
 from __future__ import annotations
 
@@ -33,7 +34,7 @@ from paper_2506_19866_amd import synth  # noqa: E402
 
 
 def make(name: str, cfg: dict | None = None, seed: int | None = None) -> dict:
-    cfg = cfg if cfg is not None else synth.CONFIGS[name]
+    cfg = cfg if cfg is not None else synth.config(name)
     base = seed if seed is not None else synth.problem_seed(name)
     min_nonzero = cfg.get("min_nonzero", 0.30)
     best = None
@@ -83,7 +84,8 @@ def main(names):
         prob = make(name)
         path = os.path.join(synth.DATA_DIR, f"{name}.npz")
         synth.save_problem(path, prob)
-        print(f"{name}: N={prob['n_nodes']} E={prob['n_edges']} P={prob['n_nodes'] + prob['n_edges']} "
+        n_params = OracleProblem(prob).n_params
+        print(f"{name}: model={prob['model']} N={prob['n_nodes']} E={prob['n_edges']} P={n_params} "
               f"C={prob['n_cond']} K={len(prob['obs_t'])} O={len(prob['obs_n'])} "
               f"max_indeg={int(np.diff(prob['row_ptr']).max())} -> {path}")
 

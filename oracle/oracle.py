@@ -44,6 +44,7 @@ class _Problem(C.Structure):
         ("n_obs_n", C.c_int32), ("obs_n", C.c_void_p),
         ("observed", C.c_void_p),
         ("step_size", C.c_int32), ("hard", C.c_int32), ("penalty", C.c_int64),
+        ("model", C.c_int32),
     ]
 
 
@@ -101,7 +102,10 @@ class OracleProblem:
     def __init__(self, prob: dict):
         self.n_nodes = int(prob["n_nodes"])
         self.n_edges = int(prob["n_edges"])
-        self.n_params = self.n_nodes + self.n_edges
+        # model 0: the synchronous ternary model (P = E + N); model 1: the
+        # paper's priority update with (w, p, t) per edge, (u, m, d) per node
+        self.model = int(prob.get("model", 0))
+        self.n_params = (3 if self.model == 1 else 1) * (self.n_nodes + self.n_edges)
         self.n_cond = int(prob["n_cond"])
         self.n_steps = int(prob["n_steps"])
         self._keep = {
@@ -119,7 +123,7 @@ class OracleProblem:
             self.n_cond, _ptr(k["init"]), _ptr(k["clamp"]), self.n_steps,
             len(k["obs_t"]), _ptr(k["obs_t"]), len(k["obs_n"]), _ptr(k["obs_n"]),
             _ptr(k["observed"]), int(prob.get("step_size", 1)), int(prob.get("hard", 1)),
-            int(prob.get("penalty", 0)))
+            int(prob.get("penalty", 0)), self.model)
         self.ref = C.byref(self.struct)
 
     # -- model -------------------------------------------------------------

@@ -15,6 +15,8 @@ constraints; synchronous reading, a_e = p*w with t = 1, theta subtracted):
     M(x)     = sum over (condition, observed time, observed node) of W * |S - R|
     V(x)     = #(nodes with no non-zero out-edge) + #(nodes with no +1 in-edge)
     cost(x)  = M(x) + lambda * V(x),  lambda = 1 + 2 * sum(W) unless given
+
+The priority-update model (prob["model"] == 1) is stated in _simulate_priority.
 """
 from __future__ import annotations
 
@@ -30,8 +32,65 @@ def _edges(prob):
     return out
 
 
+def _simulate_priority(prob, x):
+    """The priority update (§2.1 image with weight, polarity and threshold;
+    §2.2 speed, memory and step size), stated per node as a small record:
+
+        K_i       = sum over in-edges e = (j -> i) of (s_j // t_e) * w_e * p_e
+        wants     = clamp(K_i, 0, 2) != s_i          (from the states of t-1)
+        streak    = consecutive steps with 'wants' (reset when it fails)
+        ready     = wants and streak >= m_i + 1
+        priority  = u_i * (steps since the node last moved, or since t = 0)
+        the ready nodes whose priority equals the largest one move towards
+        clamp(K_i, 0, 2) by at most d_i levels and restart both counts.
+    """
+    N = int(prob["n_nodes"])
+    E = int(prob["n_edges"])
+    T = int(prob["n_steps"])
+    C = int(prob["n_cond"])
+    x = [int(v) for v in x]
+    w, pol, thr = x[:E], x[E:2 * E], x[2 * E:3 * E]
+    speed, mem, dmax = x[3 * E:3 * E + N], x[3 * E + N:3 * E + 2 * N], x[3 * E + 2 * N:3 * E + 3 * N]
+    edges = _edges(prob)
+    init = [int(v) for v in list(prob["init"].reshape(-1))]
+    clamp = [int(v) for v in list(prob["clamp"].reshape(-1))]
+    result = []
+    for c in range(C):
+        held = {i: clamp[c * N + i] for i in range(N) if clamp[c * N + i] >= 0}
+        s = [held.get(i, init[c * N + i]) for i in range(N)]
+        nodes = [{"idle": 0, "streak": 0} for _ in range(N)]
+        traj = [list(s)]
+        for _ in range(T):
+            img = [0] * N
+            for e, (j, i) in enumerate(edges):
+                img[i] += (s[j] // thr[e]) * w[e] * pol[e]
+            goal = [min(max(v, 0), 2) for v in img]
+            ranked = {}
+            for i in range(N):
+                if i in held:
+                    continue
+                rec = nodes[i]
+                rec["idle"] += 1
+                rec["streak"] = rec["streak"] + 1 if goal[i] != s[i] else 0
+                if rec["streak"] >= mem[i] + 1:
+                    ranked.setdefault(speed[i] * rec["idle"], []).append(i)
+            new = list(s)
+            if ranked:
+                for i in ranked[max(ranked)]:
+                    gap = goal[i] - s[i]
+                    step = min(abs(gap), dmax[i])
+                    new[i] = s[i] + (step if gap > 0 else -step)
+                    nodes[i] = {"idle": 0, "streak": 0}
+            s = new
+            traj.append(list(s))
+        result.append(traj)
+    return result
+
+
 def simulate(prob, x):
     """Returns traj[c][t][i] as nested lists."""
+    if int(prob.get("model", 0)) == 1:
+        return _simulate_priority(prob, x)
     N = int(prob["n_nodes"])
     E = int(prob["n_edges"])
     T = int(prob["n_steps"])
@@ -102,12 +161,19 @@ def mismatch(prob, x):
 
 def violations(prob, x):
     N = int(prob["n_nodes"])
+    E = int(prob["n_edges"])
     edges = _edges(prob)
+    if int(prob.get("model", 0)) == 1:   # w_e != 0 counts as an edge; activating: p_e = +1 and w_e != 0
+        present = [int(x[e]) != 0 for e in range(E)]
+        activating = [present[e] and int(x[E + e]) == 1 for e in range(E)]
+    else:
+        present = [int(x[e]) != 0 for e in range(E)]
+        activating = [int(x[e]) == 1 for e in range(E)]
     v = 0
     for node in range(N):
-        if not any(j == node and int(x[e]) != 0 for e, (j, _) in enumerate(edges)):
+        if not any(j == node and present[e] for e, (j, _) in enumerate(edges)):
             v += 1
-        if not any(i == node and int(x[e]) == 1 for e, (_, i) in enumerate(edges)):
+        if not any(i == node and activating[e] for e, (_, i) in enumerate(edges)):
             v += 1
     return v
 

@@ -22,6 +22,24 @@
  *   - annealing: Table 1, with a counter-based Philox4x64-10 stream, fixed-point
  *     Metropolis thresholds, lowest-chain-id tie-break.
  *
+ * A second model, selected by ora_problem.model = 1, is the paper's own
+ * parameterisation with the priority update scheme (§2.1, §2.2), for which
+ * the readings are:
+ *   - parameters: x = [w_e] ++ [p_e] ++ [t_e] (every edge, in-CSR order) ++
+ *     [u_i] ++ [m_i] ++ [d_i] (every node), P = 3E + 3N, with w in {0,1,2},
+ *     p in {-1,0,1}, t in {1,2}, u in {1..6, 10, 11, 12}, m in {0,1,2},
+ *     d in {1,2}; the image is K_i = sum_j (s_j div t_ji) * w_ji * p_ji with
+ *     no node bias (§2.5.3 b);
+ *   - a free node is "told to update" at step t when clamp(K_i, 0, 2), from
+ *     the states of step t-1, differs from its state; it is eligible when it
+ *     has been told at more than m_i consecutive steps (this one included);
+ *     its priority is u_i times the steps since its last update (or since
+ *     t = 0); the eligible nodes of the highest priority move towards
+ *     clamp(K_i, 0, 2) by at most d_i levels, and their step and telling
+ *     counts restart; every other node keeps its state;
+ *   - constraints: (a) a node needs an out-edge with w != 0; (b) a node needs
+ *     an in-edge with p = +1 and w != 0 (§2.5.3).
+ *
  * Nothing here is blocked, fused or reordered: one candidate is one full
  * re-simulation, exactly as Table 1 states.
  */
@@ -47,6 +65,7 @@ typedef struct {
   int32_t step_size;      /* d in {1,2} */
   int32_t hard;           /* 1: a proposal that breaks a constraint is rejected */
   int64_t penalty;        /* lambda; <= 0 selects 1 + 2*sum(W) */
+  int32_t model;          /* 0: synchronous ternary model; 1: the paper's priority update (step_size unused) */
 } ora_problem;
 
 /* ------------------------------------------------------------------------ */
@@ -86,7 +105,12 @@ void ora_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t ou
 /* ------------------------------------------------------------------------ */
 /* Model                                                                     */
 /* ------------------------------------------------------------------------ */
-int64_t ora_n_params(const ora_problem *p) { return (int64_t)p->n_edges + p->n_nodes; }
+int64_t ora_n_params(const ora_problem *p) {
+  return p->model == 1 ? 3 * (int64_t)p->n_edges + 3 * (int64_t)p->n_nodes : (int64_t)p->n_edges + p->n_nodes;
+}
+
+/* Speed values of the priority model (§2.2): slow 1..6, fast 10..12. */
+static const int kSpeeds[9] = {1, 2, 3, 4, 5, 6, 10, 11, 12};
 
 /* One condition: trajectory s(t) for t = 0..T_s, written to traj[(T_s+1)*N].
  * §2.1: the image of node i is the sum over its regulators j of (a_ji * s_j),
@@ -125,10 +149,66 @@ static void simulate_condition(const ora_problem *p, const int8_t *x, int c, int
   }
 }
 
+/* One condition under the priority update (§2.1 image with w, p, t; §2.2
+ * priority scheme with u, m, d; readings in the header). */
+static void simulate_condition_priority(const ora_problem *p, const int8_t *x, int c, int8_t *traj) {
+  const int N = p->n_nodes, E = p->n_edges, T = p->n_steps;
+  const int8_t *w = x, *pol = x + E, *thr = x + 2 * E;
+  const int8_t *speed = x + 3 * E, *memory = x + 3 * E + N, *dstep = x + 3 * E + 2 * N;
+  const int8_t *clamp = p->clamp + (size_t)c * N;
+  const int8_t *init = p->init + (size_t)c * N;
+  int *image = (int *)malloc(sizeof(int) * (size_t)N);
+  int *since = (int *)calloc((size_t)N, sizeof(int));   /* steps since the last update */
+  int *told = (int *)calloc((size_t)N, sizeof(int));    /* consecutive steps told to update */
+  int *prio = (int *)malloc(sizeof(int) * (size_t)N);
+  for (int i = 0; i < N; ++i) traj[i] = clamp[i] >= 0 ? clamp[i] : init[i];
+  for (int t = 1; t <= T; ++t) {
+    const int8_t *prev = traj + (size_t)(t - 1) * N;
+    int8_t *next = traj + (size_t)t * N;
+    for (int i = 0; i < N; ++i) {
+      int k = 0;
+      for (int e = p->row_ptr[i]; e < p->row_ptr[i + 1]; ++e) k += (prev[p->src[e]] / thr[e]) * w[e] * pol[e];
+      image[i] = k;
+    }
+    int best = 0;
+    for (int i = 0; i < N; ++i) {
+      prio[i] = 0;
+      if (clamp[i] >= 0) continue;
+      since[i] += 1;
+      const int target = image[i] < 0 ? 0 : (image[i] > 2 ? 2 : image[i]);
+      if (target != prev[i]) {
+        told[i] += 1;
+        if (told[i] > memory[i]) prio[i] = speed[i] * since[i];
+      } else {
+        told[i] = 0;
+      }
+      if (prio[i] > best) best = prio[i];
+    }
+    for (int i = 0; i < N; ++i) {
+      next[i] = prev[i];
+      if (best == 0 || prio[i] != best) continue;
+      const int target = image[i] < 0 ? 0 : (image[i] > 2 ? 2 : image[i]);
+      const int dist = target > prev[i] ? target - prev[i] : prev[i] - target;
+      const int move = dist < dstep[i] ? dist : dstep[i];
+      next[i] = (int8_t)(prev[i] + (target > prev[i] ? move : -move));
+      since[i] = 0;
+      told[i] = 0;
+    }
+  }
+  free(image); free(since); free(told); free(prio);
+}
+
+static void simulate_one(const ora_problem *p, const int8_t *x, int c, int8_t *traj) {
+  if (p->model == 1)
+    simulate_condition_priority(p, x, c, traj);
+  else
+    simulate_condition(p, x, c, traj);
+}
+
 /* traj: [C][T_s+1][N] */
 void ora_simulate(const ora_problem *p, const int8_t *x, int8_t *traj) {
   const size_t per = (size_t)(p->n_steps + 1) * p->n_nodes;
-  for (int c = 0; c < p->n_cond; ++c) simulate_condition(p, x, c, traj + per * c);
+  for (int c = 0; c < p->n_cond; ++c) simulate_one(p, x, c, traj + per * c);
 }
 
 /* Gradient weight of observation (c, k, o), §2.3 (gradient matrix G): the first
@@ -160,7 +240,7 @@ int64_t ora_mismatch(const ora_problem *p, const int8_t *x) {
   int8_t *traj = (int8_t *)malloc((size_t)(T + 1) * N);
   int64_t m = 0;
   for (int c = 0; c < p->n_cond; ++c) {
-    simulate_condition(p, x, c, traj);
+    simulate_one(p, x, c, traj);
     for (int k = 0; k < K; ++k)
       for (int o = 0; o < O; ++o) {
         int s = traj[(size_t)p->obs_t[k] * N + p->obs_n[o]];
@@ -176,15 +256,16 @@ int64_t ora_mismatch(const ora_problem *p, const int8_t *x) {
  * (b) every node needs an incoming activating edge (a = +1).  Counts the
  * nodes that fail (a) plus the nodes that fail (b). */
 int32_t ora_violations(const ora_problem *p, const int8_t *x) {
-  const int N = p->n_nodes;
+  const int N = p->n_nodes, E = p->n_edges;
+  const int pri = p->model == 1;
   int32_t v = 0;
   for (int i = 0; i < N; ++i) {
     int has_out = 0, has_act_in = 0;
     for (int j = 0; j < N; ++j)
       for (int e = p->row_ptr[j]; e < p->row_ptr[j + 1]; ++e)
-        if (p->src[e] == i && x[e] != 0) has_out = 1;
+        if (p->src[e] == i && x[e] != 0) has_out = 1;   /* a_e != 0, or w_e != 0 */
     for (int e = p->row_ptr[i]; e < p->row_ptr[i + 1]; ++e)
-      if (x[e] == 1) has_act_in = 1;
+      if (pri ? (x[E + e] == 1 && x[e] != 0) : x[e] == 1) has_act_in = 1;
     v += !has_out;
     v += !has_act_in;
   }
@@ -249,6 +330,32 @@ void ora_draw(uint64_t seed, uint64_t g, uint64_t chain, uint64_t net, uint64_t 
 int64_t ora_propose(const ora_problem *p, const int8_t *x, const uint64_t u[4], int8_t *new_value) {
   const int64_t P = ora_n_params(p);
   int64_t i = (int64_t)(((u[0] >> 32) * (uint64_t)P) >> 32);
+  if (p->model == 1) {
+    /* the element's domain, as codes 0..k-1; one of the k-1 other codes,
+     * uniformly (for k = 3 the same rule as the ternary model) */
+    const int64_t E = p->n_edges, N = p->n_nodes;
+    int k, code;
+    if (i < E) { k = 3; code = x[i]; }                       /* w in {0,1,2} */
+    else if (i < 2 * E) { k = 3; code = x[i] + 1; }          /* p in {-1,0,1} */
+    else if (i < 3 * E) { k = 2; code = x[i] - 1; }          /* t in {1,2} */
+    else if (i < 3 * E + N) {                                /* u in {1..6,10,11,12} */
+      k = 9;
+      for (code = 0; code < 8 && kSpeeds[code] != x[i]; ++code) {
+      }
+    } else if (i < 3 * E + 2 * N) { k = 3; code = x[i]; }    /* m in {0,1,2} */
+    else { k = 2; code = x[i] - 1; }                         /* d in {1,2} */
+    const int step = 1 + (int)(((u[1] >> 32) * (uint64_t)(k - 1)) >> 32);
+    const int nc = (code + step) % k;
+    int v;
+    if (i < E) v = nc;
+    else if (i < 2 * E) v = nc - 1;
+    else if (i < 3 * E) v = nc + 1;
+    else if (i < 3 * E + N) v = kSpeeds[nc];
+    else if (i < 3 * E + 2 * N) v = nc;
+    else v = nc + 1;
+    *new_value = (int8_t)v;
+    return i;
+  }
   int is_edge = i < p->n_edges;
   int code = is_edge ? x[i] + 1 : x[i];           /* a in {-1,0,1} -> {0,1,2} */
   int step = 1 + (int)(u[1] >> 63);               /* +1 or +2 (mod 3): never a no-op */
@@ -437,6 +544,7 @@ int ora_run(const ora_problem *p, const ora_run_args *args, const int8_t *x0,
 /* Returns the minimum cost; writes the first minimiser and the number of    */
 /* minimisers; costs[3^P] (optional) receives every cost.                    */
 /* ------------------------------------------------------------------------ */
+/* (ternary model only: model 0) */
 int64_t ora_brute_force(const ora_problem *p, int8_t *argmin_x, int64_t *n_minima, int64_t *costs) {
   const int64_t P = ora_n_params(p);
   int64_t total = 1;

@@ -140,6 +140,57 @@ def feasible_params(rng, n: int, row_ptr: np.ndarray, src: np.ndarray) -> np.nda
     return x
 
 
+# Parameters of the paper's own model with the priority update (§2.1, §2.2):
+# x = [w_e] ++ [p_e] ++ [t_e] ++ [u_i] ++ [m_i] ++ [d_i], P = 3E + 3N.
+MODEL_SYNCHRONOUS, MODEL_PRIORITY = 0, 1
+SPEEDS_SLOW = (1, 2, 3, 4, 5, 6)
+SPEEDS_FAST = (10, 11, 12)
+
+
+def priority_random_params(rng, n: int, n_edges: int, n_nodes: int, fast_fraction: float = 1.0 / 3.0) -> np.ndarray:
+    """Arbitrary priority-model vectors (constraints not enforced): w in
+    {0,1,2}, p in {-1,0,1}, t in {1,2}; per node a slow or (with probability
+    fast_fraction, one third as in §2.5.2) fast speed u, memory m in {0,1,2}
+    and step size d in {1,2}."""
+    E, N = n_edges, n_nodes
+    x = np.empty((n, 3 * E + 3 * N), dtype=np.int8)
+    x[:, :E] = rng.integers(0, 3, size=(n, E))
+    x[:, E:2 * E] = rng.integers(-1, 2, size=(n, E))
+    x[:, 2 * E:3 * E] = rng.integers(1, 3, size=(n, E))
+    fast = rng.random((n, N)) < fast_fraction
+    x[:, 3 * E:3 * E + N] = np.where(fast, rng.choice(np.array(SPEEDS_FAST, dtype=np.int8), size=(n, N)),
+                                     rng.choice(np.array(SPEEDS_SLOW, dtype=np.int8), size=(n, N)))
+    x[:, 3 * E + N:3 * E + 2 * N] = rng.integers(0, 3, size=(n, N))
+    x[:, 3 * E + 2 * N:] = rng.integers(1, 3, size=(n, N))
+    return x
+
+
+def priority_feasible_params(rng, n: int, row_ptr: np.ndarray, src: np.ndarray) -> np.ndarray:
+    """Priority-model vectors that satisfy §2.5.3 by construction: for every
+    node one uniformly chosen out-edge gets w in {1,2} and one uniformly chosen
+    in-edge gets w in {1,2} and p = +1 (a non-zero w keeps the out-edge
+    property of an edge chosen both ways)."""
+    row_ptr = np.asarray(row_ptr)
+    src = np.asarray(src)
+    N = len(row_ptr) - 1
+    E = len(src)
+    x = priority_random_params(rng, n, E, N)
+    rows = np.arange(n)
+    for v in range(N):
+        outs = np.flatnonzero(src == v)
+        if len(outs) == 0:
+            raise ValueError(f"node {v} has no out-edge: no feasible vector exists")
+        x[rows, outs[rng.integers(0, len(outs), size=n)]] = rng.integers(1, 3, size=n)
+    for v in range(N):
+        lo, hi = int(row_ptr[v]), int(row_ptr[v + 1])
+        if hi == lo:
+            raise ValueError(f"node {v} has no in-edge: no feasible vector exists")
+        pick = rng.integers(lo, hi, size=n)
+        x[rows, pick] = rng.integers(1, 3, size=n)
+        x[rows, E + pick] = 1
+    return x
+
+
 # ---------------------------------------------------------------------------
 # experimental design
 # ---------------------------------------------------------------------------
@@ -203,6 +254,25 @@ CONFIGS = {
 }
 
 
+# The paper's own model (priority update, P = 3E + 3N) at the sizes of its two
+# networks (§2.5): one condition, 20 time points including the initial state,
+# every one observed.
+PRIORITY_CONFIGS = {
+    # tiny: 6 nodes, 12 edges, 54 parameters
+    "q1": dict(model=MODEL_PRIORITY, n_nodes=6, n_edges=12, topology="bounded_indegree", n_cond=2, clamps=(0, 0),
+               n_steps=10, n_obs=4, noise=0.0,
+               chains=64, stages=60, steps_per_stage=100, T0=2.0, T_end=0.01),
+    # HPG axis: 9 nodes, 25 edges, 102 parameters, 5 observed nodes (§2.5.1)
+    "q2": dict(model=MODEL_PRIORITY, n_nodes=9, n_edges=25, topology="cycle_plus_uniform", n_cond=1, clamps=(0, 0),
+               n_steps=19, n_obs=5, noise=0.10,
+               chains=4096, stages=100, steps_per_stage=500, T0=2.0, T_end=0.01),
+    # Mtb host-pathogen: 63 nodes, 178 edges, 723 parameters, 35 observed nodes (§2.5.2)
+    "q3": dict(model=MODEL_PRIORITY, n_nodes=63, n_edges=178, topology="cycle_plus_uniform", n_cond=1, clamps=(0, 0),
+               n_steps=19, n_obs=35, noise=0.0,
+               chains=16384, stages=200, steps_per_stage=500, T0=2.0, T_end=0.01),
+}
+
+
 # Batched uneven workload: 256 independent networks of 10-150 nodes, each with
 # its own conditions and data, 256 chains per network in one persistent launch.
 BATCH = dict(name="c4", n_networks=256, nodes=(10, 150), mean_indegree=(2.0, 5.0), conditions=(4, 16),
@@ -234,7 +304,7 @@ def load_batch(name: str = "c4") -> list:
         pre = f"n{i}_"
         prob = {k[len(pre):]: v for k, v in files.items() if k.startswith(pre)}
         for k in _INT_KEYS:
-            prob[k] = int(prob[k])
+            prob[k] = int(prob[k]) if k in prob else 0
         out.append(prob)
     return out
 
@@ -258,11 +328,15 @@ def batch_schedule() -> dict:
 
 
 def problem_seed(name: str) -> int:
-    return 1000 + int(name[1:])
+    return (1100 if name.startswith("q") else 1000) + int(name[1:])
 
 
 def run_seed(name: str) -> int:
-    return 2000 + int(name[1:])
+    return (2100 if name.startswith("q") else 2000) + int(name[1:])
+
+
+def config(name: str) -> dict:
+    return PRIORITY_CONFIGS[name] if name in PRIORITY_CONFIGS else CONFIGS[name]
 
 
 def cooling_factor(T0: float, T_end: float, n_stages: int) -> float:
@@ -285,18 +359,23 @@ def make_structure(cfg: dict, rng) -> dict:
         row_ptr, src = topology_preferential(rng, N, E)
     else:
         raise ValueError(topo)
-    hidden = feasible_params(rng, 1, row_ptr, src)[0]
+    priority = cfg.get("model", MODEL_SYNCHRONOUS) == MODEL_PRIORITY
+    hidden = (priority_feasible_params if priority else feasible_params)(rng, 1, row_ptr, src)[0]
     init, clamp = conditions(rng, N, cfg["n_cond"], cfg["clamps"])
+    if priority:  # every time point observed, the initial state included (§2.5)
+        obs_t = np.arange(cfg["n_steps"] + 1, dtype=np.int32)
+    else:
+        obs_t = observation_times(cfg["n_steps"], cfg["n_times"])
     return dict(n_nodes=N, n_edges=E, row_ptr=row_ptr, src=src, n_cond=cfg["n_cond"],
-                init=init, clamp=clamp, n_steps=cfg["n_steps"],
-                obs_t=observation_times(cfg["n_steps"], cfg["n_times"]),
-                step_size=1, hard=1, penalty=0, hidden=hidden)
+                init=init, clamp=clamp, n_steps=cfg["n_steps"], obs_t=obs_t,
+                step_size=1, hard=1, penalty=0, model=MODEL_PRIORITY if priority else MODEL_SYNCHRONOUS,
+                hidden=hidden)
 
 
 # ---------------------------------------------------------------------------
 # stored workloads
 # ---------------------------------------------------------------------------
-_INT_KEYS = ("n_nodes", "n_edges", "n_cond", "n_steps", "step_size", "hard", "penalty")
+_INT_KEYS = ("n_nodes", "n_edges", "n_cond", "n_steps", "step_size", "hard", "penalty", "model")
 
 
 def save_problem(path: str, prob: dict) -> None:
@@ -309,7 +388,7 @@ def load_problem(path: str) -> dict:
     with np.load(path, allow_pickle=False) as z:
         out = {k: z[k] for k in z.files}
     for k in _INT_KEYS:
-        out[k] = int(out[k])
+        out[k] = int(out[k]) if k in out else 0  # files written before "model" existed: model 0
     return out
 
 
@@ -321,18 +400,20 @@ def load_workload(name: str) -> dict:
 
 def start_vectors(name: str, prob: dict, n_chains: int) -> np.ndarray:
     """Per-chain starting vectors of a workload's runs (feasible)."""
-    return feasible_params(rng_for(run_seed(name) + 7), n_chains, prob["row_ptr"], prob["src"])
+    gen = priority_feasible_params if prob.get("model", 0) == MODEL_PRIORITY else feasible_params
+    return gen(rng_for(run_seed(name) + 7), n_chains, prob["row_ptr"], prob["src"])
 
 
 def bench_schedule(name: str) -> dict:
-    cfg = CONFIGS[name]
+    cfg = config(name)
     return dict(n_chains=cfg["chains"], n_stages=cfg["stages"],
                 steps_per_stage=cfg["steps_per_stage"], T0=cfg["T0"],
                 rho=cooling_factor(cfg["T0"], cfg["T_end"], cfg["stages"]), seed=run_seed(name))
 
 
 def n_flips(cfg: dict) -> int:
-    n = cfg["n_cond"] * cfg["n_times"] * cfg["n_obs"]
+    n_times = cfg["n_steps"] + 1 if cfg.get("model", MODEL_SYNCHRONOUS) == MODEL_PRIORITY else cfg["n_times"]
+    n = cfg["n_cond"] * n_times * cfg["n_obs"]
     return int(round(cfg["noise"] * n))
 
 

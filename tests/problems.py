@@ -18,7 +18,7 @@ def golden(name: str) -> dict:
 
 
 def from_edges(n_nodes, edges_src_dst, *, init, clamp=None, n_steps=5, obs_t=(1,), obs_n=(0,),
-               observed=None, step_size=1, hard=1, penalty=0):
+               observed=None, step_size=1, hard=1, penalty=0, model=0):
     """Problem dict from an explicit edge list (one condition per row of init).
     Returns (prob, perm) where perm[k] is the index of the k-th given edge in
     the canonical (target-grouped) parameter order."""
@@ -37,7 +37,7 @@ def from_edges(n_nodes, edges_src_dst, *, init, clamp=None, n_steps=5, obs_t=(1,
     prob = dict(n_nodes=n_nodes, n_edges=len(src), row_ptr=row_ptr, src=src, n_cond=C,
                 init=init, clamp=clamp, n_steps=n_steps, obs_t=obs_t, obs_n=obs_n,
                 observed=np.asarray(observed, dtype=np.int8).reshape(C, len(obs_t), len(obs_n)),
-                step_size=step_size, hard=hard, penalty=penalty)
+                step_size=step_size, hard=hard, penalty=penalty, model=model)
     return prob, perm
 
 

@@ -7,7 +7,7 @@ from oracle import make_workloads
 from paper_2506_19866_amd import synth
 
 
-@pytest.mark.parametrize("name", ["c1", "c2", "c3"])
+@pytest.mark.parametrize("name", ["c1", "c2", "c3", "q1", "q2", "q3"])
 def test_stored_workload_regenerates(name):
     stored = synth.load_workload(name)
     fresh = make_workloads.make(name)
@@ -37,3 +37,17 @@ def test_workload_shapes(name, N, E, P, C):
     assert w["observed"].shape == (C, cfg["n_times"], cfg["n_obs"])
     flips = int((w["observed"] != w["clean"]).sum())
     assert flips == synth.n_flips(cfg)
+
+
+@pytest.mark.parametrize("name,N,E,P,C,K,O", [("q1", 6, 12, 54, 2, 11, 4), ("q2", 9, 25, 102, 1, 20, 5),
+                                            ("q3", 63, 178, 723, 1, 20, 35)])
+def test_priority_workload_shapes(name, N, E, P, C, K, O):
+    w = synth.load_workload(name)
+    assert w["model"] == synth.MODEL_PRIORITY
+    assert (w["n_nodes"], w["n_edges"], 3 * (w["n_nodes"] + w["n_edges"]), w["n_cond"]) == (N, E, P, C)
+    assert w["observed"].shape == (C, K, O) and len(w["hidden"]) == P
+    assert w["obs_t"].tolist() == list(range(K))
+    cfg = synth.PRIORITY_CONFIGS[name]
+    assert int((w["observed"] != w["clean"]).sum()) == synth.n_flips(cfg)
+    u = w["hidden"][3 * E:3 * E + N]
+    assert set(u.tolist()) <= set(synth.SPEEDS_SLOW + synth.SPEEDS_FAST)
