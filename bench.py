@@ -57,6 +57,18 @@ def algorithmic_alu_ops(prob: dict) -> int:
     return 2 * C * T * N + 2 * C * K * O
 
 
+def algorithmic_alu_ops_priority(prob: dict) -> int:
+    """The same count for the priority-update model: per (condition, step,
+    edge) 2 ops (the regulator term's multiply-add, its threshold division
+    taken as an operand choice), per (condition, step, node) 6 ops (bound the
+    image, the told test, the memory count, the priority product, the
+    comparison with the step's highest priority, the bounded move), per
+    observation term 2 ops."""
+    C, T, N, E = prob["n_cond"], prob["n_steps"], prob["n_nodes"], prob["n_edges"]
+    K, O = len(prob["obs_t"]), len(prob["obs_n"])
+    return 2 * C * T * E + 6 * C * T * N + 2 * C * K * O
+
+
 def traffic_from_profiles(launch_key: str):
     """HBM bytes per stage-kernel launch from the committed PMC summary, or
     None when it is missing or the kernel sources changed since."""
@@ -341,8 +353,9 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200, help="timed temperature stages")
     ap.add_argument("--warmup", type=int, default=2, help="untimed stages on a discarded run")
-    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4"],
-                    help="c4 = the batched workload (256 uneven networks, one persistent launch per stage)")
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "q1", "q2", "q3"],
+                    help="c4 = the batched workload (256 uneven networks, one persistent launch per stage); "
+                         "q1-q3 = the paper's priority-update model (q2 HPG-sized, q3 Mtb-sized)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--mode", default="throughput", choices=["throughput", "learned", "learned-cost", "sweep"],
@@ -395,10 +408,11 @@ def main() -> int:
     prob = synth.load_workload(name)
     sched = synth.bench_schedule(name)
     n, L = sched["n_chains"], sched["steps_per_stage"]
-    log(f"[bench] workload {name}: N={prob['n_nodes']} E={prob['n_edges']} "
-        f"P={prob['n_nodes'] + prob['n_edges']} C={prob['n_cond']} chains={n} L={L}")
+    priority = prob.get("model", 0) == synth.MODEL_PRIORITY
     x0 = torch.from_numpy(synth.start_vectors(name, prob, n)).cuda()
     P = sa.Problem(prob)
+    log(f"[bench] workload {name}: N={prob['n_nodes']} E={prob['n_edges']} "
+        f"P={P.n_params} C={prob['n_cond']} chains={n} L={L}")
     torch.cuda.synchronize()
 
     if args.warmup > 0:
@@ -426,24 +440,34 @@ def main() -> int:
 
     # roofline of the stage kernel: algorithmic ALU work of the simulations it
     # ran (one per feasible proposal plus one per chain at stage start)
-    per_sim = algorithmic_alu_ops(prob)
+    per_sim = algorithmic_alu_ops_priority(prob) if priority else algorithmic_alu_ops(prob)
     sims = (n * L - stats["infeasible"].astype(np.float64)) + n
     ops_per_launch = float(np.mean(sims)) * per_sim
     avg_launch_s = float(np.mean(stage_ms)) * 1e-3
     achieved = ops_per_launch / avg_launch_s
     launch_key = f"{name}:{n}x{L}"
+    if priority:
+        lc = 16 if prob["n_nodes"] <= 16 else 32 if prob["n_nodes"] <= 32 else 64
+        kernel = f"pr_stage_kernel<{lc}>"
+        traffic = None
+        model = (f"the paper's priority-update model, {prob['n_nodes']} nodes, {prob['n_edges']} edges, "
+                 f"{P.n_params} params (w, p, t per edge; u, m, d per node)")
+    else:
+        kernel = f"stage_kernel<{info['tiles_m']},{info['frags_k']},{int(prob.get('step_size', 1))}>"
+        traffic = traffic_from_profiles(launch_key)
+        model = (f"Mtb-scale, {prob['n_nodes']} nodes, {prob['n_edges']} edges, {P.n_params} ternary params "
+                 f"(synchronous update)")
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK_OPS / 1e12, "unit": "TOP/s",
-                "frac": achieved / ALU_PEAK_OPS, "traffic": traffic_from_profiles(launch_key),
-                "kernel": f"stage_kernel<{info['tiles_m']},{info['frags_k']},{int(prob.get('step_size', 1))}>",
+                "frac": achieved / ALU_PEAK_OPS, "traffic": traffic, "kernel": kernel,
                 "avg_launch_ms": float(np.mean(stage_ms)),
                 "ops_per_launch": ops_per_launch}
     out = {
-        "metric": "SA chain-steps/s at 723-param scale", "value": value, "unit": "chain-steps/s",
+        "metric": "SA chain-steps/s at 723-param scale" if P.n_params == 723 else "SA chain-steps/s",
+        "value": value, "unit": "chain-steps/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed * 1e3 / args.steps,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp4",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32" if priority else "fp4",
         "data": "synthetic (seeded generator + oracle-simulated reference data, stored workload)",
-        "config": {"workload": f"{name}: Mtb-scale, {prob['n_nodes']} nodes, {prob['n_edges']} edges, "
-                               f"{prob['n_nodes'] + prob['n_edges']} ternary params, {prob['n_cond']} conditions, "
+        "config": {"workload": f"{name}: {model}, {prob['n_cond']} conditions, "
                                f"{prob['n_steps']} steps; {n} chains x {L} steps per stage, "
                                f"{args.steps} stages of a {sched['n_stages']}-stage schedule T0={sched['T0']}",
                    "chains": n, "steps_per_stage": L, "stages_timed": args.steps,

@@ -55,6 +55,24 @@ enum {
 
 enum { SA_HARD = 0, SA_PENALTY = 1 };
 
+/* The logic model of a problem.
+ * SA_MODEL_SYNCHRONOUS: every node moves at every step (the synchronous scheme
+ *   §2.2 names as the usual alternative); one ternary parameter per edge,
+ *   a in {-1,0,1} (the product p * w with w in {0,1} and threshold 1), and one
+ *   per node, theta in {0,1,2} subtracted from the image; P = E + N.
+ * SA_MODEL_PRIORITY: the paper's own model.  Per edge a weight w in {0,1,2},
+ *   a polarity p in {-1,0,1} and a threshold t in {1,2}; the image of node i
+ *   is K_i = sum over in-edges (s_j div t) * w * p (§2.1).  Per node a speed
+ *   u in {1..6, 10, 11, 12}, a memory m in {0,1,2} and a step size d in {1,2}
+ *   drive the priority update of §2.2: a free node whose clamped image differs
+ *   from its state at m + 1 consecutive steps is eligible, with priority u
+ *   times the steps since it last moved; the eligible nodes of the highest
+ *   priority move towards the image by at most d.  Constraints (§2.5.3):
+ *   (a) an out-edge with w != 0, (b) an in-edge with p = +1 and w != 0.
+ *   x = [w_e] ++ [p_e] ++ [t_e] (edges in in-CSR order) ++ [u_i] ++ [m_i] ++
+ *   [d_i]; P = 3E + 3N.  Networks of at most 64 nodes. */
+enum { SA_MODEL_SYNCHRONOUS = 0, SA_MODEL_PRIORITY = 1 };
+
 typedef struct sa_problem sa_problem;
 typedef struct sa_run sa_run;
 typedef struct sa_mlp sa_mlp; /* proposal network, see the end of this header */
@@ -80,10 +98,13 @@ typedef struct {
   int32_t constraint_mode;    /* SA_HARD: a proposal that breaks (a) or (b) is a rejected step (§2.5.3);
                                  SA_PENALTY: every proposal is scored with lambda * V */
   int32_t penalty;            /* lambda >= 0; 0 selects 1 + 2 * sum(W), larger than any mismatch */
+  int32_t model;              /* SA_MODEL_SYNCHRONOUS or SA_MODEL_PRIORITY (step_size is then unused:
+                                 each node carries its own d) */
 } sa_problem_desc;
 
 typedef struct {
-  int32_t n_params;   /* P = E + N: x = [a_e in in-CSR order] ++ [theta_0 .. theta_{N-1}] */
+  int32_t n_params;   /* P = E + N: x = [a_e in in-CSR order] ++ [theta_0 .. theta_{N-1}];
+                         P = 3E + 3N for SA_MODEL_PRIORITY (layout above) */
   int32_t n_nodes, n_edges, n_conditions, n_steps, n_obs_times, n_obs_nodes;
   int32_t weight_sum; /* sum of W over all observations */
   int32_t penalty;    /* lambda in effect */
@@ -92,7 +113,8 @@ typedef struct {
 
 /* Validates the description, precomputes the weights W and lambda and the
  * register layout of the kernels, and copies everything to the current HIP
- * device (synchronous).  Sizes handled: N <= 191, C <= 64.
+ * device (synchronous).  Sizes handled: N <= 191, C <= 64 (synchronous
+ * model); N <= 64 (priority model).
  * Errors: SA_ERR_ARG, SA_ERR_DOMAIN, SA_ERR_TOPOLOGY, SA_ERR_UNSUPPORTED,
  * SA_ERR_OVERFLOW, SA_ERR_DEVICE, SA_ERR_OOM. */
 int sa_create_problem(const sa_problem_desc *desc, sa_problem **out);
@@ -100,14 +122,15 @@ int sa_destroy_problem(sa_problem *prob);
 int sa_problem_get_info(const sa_problem *prob, sa_problem_info *info);
 
 /* cost_dev[i] = M(x_i) + lambda * V(x_i) (§2.3, §2.5.3) for the n vectors
- * x_dev[i*P .. i*P+P-1] (device, int8, a in {-1,0,1}, theta in {0,1,2}).
+ * x_dev[i*P .. i*P+P-1] (device, int8, a in {-1,0,1}, theta in {0,1,2}; or
+ * the priority model's layout and domains).
  * Values outside the domain are not checked (their cost is unspecified).
  * n = 0 is a no-op. */
 int sa_eval_cost(const sa_problem *prob, const int8_t *x_dev, int64_t n, int32_t *cost_dev, void *stream);
 
 /* traj_dev[((i*C + c)*(T_s+1) + t)*N + v] = state of node v at step t under
- * condition c for vector x_i (device, int8): the synchronous trajectories of
- * §2.2, clamped nodes held.  n = 0 is a no-op. */
+ * condition c for vector x_i (device, int8): the trajectories of §2.2 under
+ * the problem's update scheme, clamped nodes held.  n = 0 is a no-op. */
 int sa_simulate(const sa_problem *prob, const int8_t *x_dev, int64_t n, int8_t *traj_dev, void *stream);
 
 /* Annealing schedule and chains (Table 1).  Stage k runs at

@@ -117,7 +117,12 @@ static int validate(const sa_problem_desc *d) {
   if (!d->in_row_ptr || (E > 0 && !d->in_src) || !d->init_state || !d->clamp || !d->obs_times ||
       !d->obs_nodes || !d->observed)
     return fail(SA_ERR_ARG, "a required array is NULL");
-  if (d->step_size != 1 && d->step_size != 2) return fail(SA_ERR_DOMAIN, "step_size must be 1 or 2");
+  if (d->model != SA_MODEL_SYNCHRONOUS && d->model != SA_MODEL_PRIORITY)
+    return fail(SA_ERR_ARG, "unknown model %d", d->model);
+  if (d->model == SA_MODEL_SYNCHRONOUS && d->step_size != 1 && d->step_size != 2)
+    return fail(SA_ERR_DOMAIN, "step_size must be 1 or 2");
+  if (d->model == SA_MODEL_PRIORITY && N > 64)
+    return fail(SA_ERR_UNSUPPORTED, "priority model: n_nodes %d > 64", N);
   if (d->constraint_mode != SA_HARD && d->constraint_mode != SA_PENALTY)
     return fail(SA_ERR_ARG, "unknown constraint_mode %d", d->constraint_mode);
   if (d->penalty < 0) return fail(SA_ERR_DOMAIN, "penalty must be >= 0");
@@ -160,6 +165,88 @@ static int validate(const sa_problem_desc *d) {
   return SA_OK;
 }
 
+// The priority model's tables (sa_priority.h): per condition the start state
+// of every lane of a chain's segment, per (condition, step) the reference byte.
+static int create_priority(const sa_problem_desc *d, const std::vector<int> &W, long long wsum, long long lambda,
+                           long long max_cost, sa_problem **out) {
+  const int N = d->n_nodes, E = d->n_edges, C = d->n_conditions, T = d->n_steps;
+  const int K = d->n_obs_times, O = d->n_obs_nodes, P = 3 * E + 3 * N;
+  const int lc = N <= 16 ? 16 : N <= 32 ? 32 : 64;
+  std::vector<uint8_t> start((size_t)C * lc), obs((size_t)C * (T + 1) * lc, 0);
+  for (int c = 0; c < C; ++c)
+    for (int v = 0; v < lc; ++v) {
+      int val = 0, held = 1;
+      if (v < N) {
+        const int cl = d->clamp[(size_t)c * N + v];
+        held = cl >= 0;
+        val = held ? cl : d->init_state[(size_t)c * N + v];
+      }
+      start[(size_t)c * lc + v] = (uint8_t)(val | held << 2);
+    }
+  for (int c = 0; c < C; ++c)
+    for (int k = 0; k < K; ++k)
+      for (int o = 0; o < O; ++o) {
+        const size_t at = ((size_t)c * K + k) * O + o;
+        obs[((size_t)c * (T + 1) + d->obs_times[k]) * lc + d->obs_nodes[o]] =
+            (uint8_t)(d->observed[at] | W[at] << 2);
+      }
+  std::vector<int32_t> esrc(E), edst(E);
+  for (int i = 0; i < N; ++i)
+    for (int e = d->in_row_ptr[i]; e < d->in_row_ptr[i + 1]; ++e) {
+      esrc[e] = d->in_src[e];
+      edst[e] = i;
+    }
+
+  auto *pr = new sa_problem();
+  hipGetDevice(&pr->device);
+  Layout lay;
+  const size_t o_esrc = lay.take((size_t)E * 4), o_edst = lay.take((size_t)E * 4);
+  const size_t o_inptr = lay.take((size_t)(N + 1) * 4);
+  const size_t o_start = lay.take(start.size()), o_obs = lay.take(obs.size());
+  hipError_t e = hipMalloc(&pr->dmem, lay.bytes);
+  if (e != hipSuccess) {
+    delete pr;
+    return hip_fail(e, "hipMalloc(problem)");
+  }
+  std::vector<char> host(lay.bytes, 0);
+  auto put = [&](size_t off, const void *src, size_t n) {
+    if (n) memcpy(host.data() + off, src, n);
+  };
+  put(o_esrc, esrc.data(), (size_t)E * 4);
+  put(o_edst, edst.data(), (size_t)E * 4);
+  put(o_inptr, d->in_row_ptr, (size_t)(N + 1) * 4);
+  put(o_start, start.data(), start.size());
+  put(o_obs, obs.data(), obs.size());
+  e = hipMemcpy(pr->dmem, host.data(), lay.bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    hipFree(pr->dmem);
+    delete pr;
+    return hip_fail(e, "hipMemcpy(problem)");
+  }
+  const char *base = (const char *)pr->dmem;
+  sa::DevProblem &dp = pr->dev;
+  dp.N = N; dp.E = E; dp.P = P; dp.C = C; dp.T = T; dp.K = K; dp.O = O;
+  dp.hard = d->constraint_mode == SA_HARD;
+  dp.lambda = (int32_t)lambda;
+  dp.sum_w = (int32_t)wsum;
+  dp.edge_src = (const int32_t *)(base + o_esrc);
+  dp.edge_dst = (const int32_t *)(base + o_edst);
+  dp.in_ptr = (const int32_t *)(base + o_inptr);
+  dp.model = SA_MODEL_PRIORITY;
+  dp.lc = lc;
+  dp.pr_start = (const uint8_t *)(base + o_start);
+  dp.pr_obs = (const uint8_t *)(base + o_obs);
+
+  sa_problem_info &in = pr->info;
+  in.n_params = P; in.n_nodes = N; in.n_edges = E; in.n_conditions = C; in.n_steps = T;
+  in.n_obs_times = K; in.n_obs_nodes = O;
+  in.weight_sum = (int32_t)wsum;
+  in.penalty = (int32_t)lambda;
+  in.max_cost = (int32_t)max_cost;
+  *out = pr;
+  return SA_OK;
+}
+
 extern "C" int sa_create_problem(const sa_problem_desc *d, sa_problem **out) {
   if (!out) return fail(SA_ERR_ARG, "out is NULL");
   *out = nullptr;
@@ -182,6 +269,7 @@ extern "C" int sa_create_problem(const sa_problem_desc *d, sa_problem **out) {
   const long long lambda = d->penalty > 0 ? d->penalty : 1 + 2 * wsum;
   const long long max_cost = 2 * wsum + lambda * 2 * (long long)N;
   if (max_cost >= (1ll << 31) - 1) return fail(SA_ERR_OVERFLOW, "largest cost %lld does not fit int32", max_cost);
+  if (d->model == SA_MODEL_PRIORITY) return create_priority(d, W, wsum, lambda, max_cost, out);
 
   // tiles: nm m-tiles of 16 rows hold the nodes, nk k-fragments of 128
   // columns (32 slots per lane group) hold nodes + bias; layouts with two
@@ -412,7 +500,10 @@ extern "C" int sa_eval_cost(const sa_problem *p, const int8_t *x, int64_t n, int
   if (n == 0) return SA_OK;
   if (!x || !cost) return fail(SA_ERR_ARG, "NULL device pointer");
   SA_HIP(hipSetDevice(p->device), "hipSetDevice");
-  SA_HIP((hipError_t)sa::launch_eval(p->dev, x, n, cost, stream), "eval launch");
+  if (p->dev.model == SA_MODEL_PRIORITY)
+    SA_HIP((hipError_t)sa::launch_priority_eval(p->dev, x, n, cost, stream), "eval launch");
+  else
+    SA_HIP((hipError_t)sa::launch_eval(p->dev, x, n, cost, stream), "eval launch");
   return SA_OK;
 }
 
@@ -422,13 +513,31 @@ extern "C" int sa_simulate(const sa_problem *p, const int8_t *x, int64_t n, int8
   if (n == 0) return SA_OK;
   if (!x || !traj) return fail(SA_ERR_ARG, "NULL device pointer");
   SA_HIP(hipSetDevice(p->device), "hipSetDevice");
-  SA_HIP((hipError_t)sa::launch_simulate(p->dev, x, n, traj, stream), "simulate launch");
+  if (p->dev.model == SA_MODEL_PRIORITY)
+    SA_HIP((hipError_t)sa::launch_priority_simulate(p->dev, x, n, traj, stream), "simulate launch");
+  else
+    SA_HIP((hipError_t)sa::launch_simulate(p->dev, x, n, traj, stream), "simulate launch");
   return SA_OK;
 }
 
 // ---------------------------------------------------------------------------
 // runs
 // ---------------------------------------------------------------------------
+static int launch_cost(const sa::DevProblem &dp, const int8_t *x, int64_t n, int32_t *cost, hipStream_t s) {
+  return dp.model == SA_MODEL_PRIORITY ? sa::launch_priority_eval(dp, x, n, cost, s) : sa::launch_eval(dp, x, n, cost, s);
+}
+
+// Domain of element k of a parameter vector (§2.1, §2.2).
+static bool in_domain(const sa::DevProblem &dp, int k, int v) {
+  const int E = dp.E, N = dp.N;
+  if (dp.model != SA_MODEL_PRIORITY) return k < E ? (v >= -1 && v <= 1) : (v >= 0 && v <= 2);
+  if (k < E) return v >= 0 && v <= 2;                                        // w
+  if (k < 2 * E) return v >= -1 && v <= 1;                                   // p
+  if (k < 3 * E) return v == 1 || v == 2;                                    // t
+  if (k < 3 * E + N) return (v >= 1 && v <= 6) || (v >= 10 && v <= 12);      // u
+  if (k < 3 * E + 2 * N) return v >= 0 && v <= 2;                            // m
+  return v == 1 || v == 2;                                                   // d
+}
 // Metropolis threshold of Table 1 in fixed point: floor(2^32 exp(-D/T)),
 // clipped to 2^32 - 1; tabulated for D = 1 .. dcap (the last non-zero).
 static void tau_table(double T, int32_t max_delta, std::vector<uint32_t> &tab, int32_t &dcap) {
@@ -546,6 +655,8 @@ static int enqueue_stage(sa_run *r, int32_t st, hipStream_t stream) {
       sa::LearnedArgs la = r->la;
       la.lt = r->lt[st];
       SA_HIP((hipError_t)sa::launch_learned_stage(pb, a, la, stream), "learned stage launch");
+    } else if (pb.model == SA_MODEL_PRIORITY) {
+      SA_HIP((hipError_t)sa::launch_priority_stage(pb, a, stream), "priority stage launch");
     } else {
       SA_HIP((hipError_t)sa::launch_stage(pb, a, stream), "stage launch");
     }
@@ -677,6 +788,12 @@ extern "C" int sa_run_create(sa_problem *const *probs, int32_t n_probs, const sa
       return fail(SA_ERR_UNSUPPORTED, "learned proposal / trace: %d observed times (at most 42)", dp.K);
     if (learned && desc->model->device != probs[0]->device) return fail(SA_ERR_ARG, "model on another device");
   }
+  const bool priority = probs[0]->dev.model == SA_MODEL_PRIORITY;
+  for (int i = 0; i < n_probs; ++i)
+    if ((probs[i]->dev.model == SA_MODEL_PRIORITY) != priority || (priority && n_probs > 1))
+      return fail(SA_ERR_UNSUPPORTED, "the priority model runs one problem per run");
+  if (priority && (desc->kernel != SA_KERNEL_AUTO || learned || traced))
+    return fail(SA_ERR_UNSUPPORTED, "the priority model runs on its own stage kernel with plain proposals");
   const int device = probs[0]->device;
   for (int i = 1; i < n_probs; ++i)
     if (probs[i]->device != device) return fail(SA_ERR_ARG, "problems on different devices");
@@ -737,6 +854,12 @@ extern "C" int sa_run_create(sa_problem *const *probs, int32_t n_probs, const sa
       const int64_t g0 = (int64_t)desc->first_stage * desc->steps_per_stage;
       la.trace_first = (g0 + desc->trace_every - 1) / desc->trace_every * desc->trace_every;
     }
+  } else if (priority) {
+    const size_t smem = sa::priority_stage_smem_bytes(probs[0]->dev);
+    if (smem > 64 * 1024) {
+      free_run(r);
+      return fail(SA_ERR_UNSUPPORTED, "priority stage kernel needs %zu bytes of LDS (> 64 KiB)", smem);
+    }
   } else if (!persistent) {
     const size_t smem = sa::stage_smem_bytes(probs[0]->dev, sa::stage_waves_per_block(probs[0]->dev));
     if (smem > 64 * 1024) {
@@ -754,11 +877,11 @@ extern "C" int sa_run_create(sa_problem *const *probs, int32_t n_probs, const sa
     return hip_fail(e, "copy x0");
   }
   for (int i = 0; i < n_probs; ++i) {
-    const int P = probs[i]->dev.P, E = probs[i]->dev.E;
+    const int P = probs[i]->dev.P;
     for (int64_t c = 0; c < n; ++c)
       for (int k = 0; k < P; ++k) {
         const int v = hx[(size_t)(r->x_off[i] + c * P + k)];
-        if (k < E ? (v < -1 || v > 1) : (v < 0 || v > 2)) {
+        if (!in_domain(probs[i]->dev, k, v)) {
           free_run(r);
           return fail(SA_ERR_DOMAIN, "x0 problem %d chain %lld parameter %d = %d", i, (long long)c, k, v);
         }
@@ -816,10 +939,10 @@ extern "C" int sa_run_create(sa_problem *const *probs, int32_t n_probs, const sa
     const sa::DevProblem &dp = probs[i]->dev;
     if (!dp.hard) continue;
     int32_t *c1 = r->cbest, *c0 = (int32_t *)r->cstats;
-    e = (hipError_t)sa::launch_eval(dp, r->x0 + r->x_off[i], n, c1, s);
+    e = (hipError_t)launch_cost(dp, r->x0 + r->x_off[i], n, c1, s);
     sa::DevProblem m = dp;
     m.lambda = 0;
-    if (e == hipSuccess) e = (hipError_t)sa::launch_eval(m, r->x0 + r->x_off[i], n, c0, s);
+    if (e == hipSuccess) e = (hipError_t)launch_cost(m, r->x0 + r->x_off[i], n, c0, s);
     std::vector<int32_t> h1((size_t)n), h0((size_t)n);
     if (e == hipSuccess) e = hipMemcpyAsync(h1.data(), c1, (size_t)n * 4, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipMemcpyAsync(h0.data(), c0, (size_t)n * 4, hipMemcpyDeviceToHost, s);
@@ -975,7 +1098,10 @@ extern "C" int sa_run_get_info(sa_run *r, sa_run_info *info) {
   if (!r || !info) return fail(SA_ERR_ARG, "NULL argument");
   info->n_probs = (int32_t)r->probs.size();
   info->kernel = r->persistent ? SA_KERNEL_PERSISTENT : SA_KERNEL_AUTO;
-  info->chains_per_block = r->persistent ? r->waves : sa::stage_waves_per_block(r->probs[0]->dev);
+  const sa::DevProblem &dp0 = r->probs[0]->dev;
+  info->chains_per_block = r->persistent                      ? r->waves
+                           : dp0.model == SA_MODEL_PRIORITY ? 4 * (64 / dp0.lc)
+                                                            : sa::stage_waves_per_block(dp0);
   info->stages_launched = r->launched;
   info->tiles_m = r->probs[0]->dev.nm;
   info->frags_k = r->probs[0]->dev.nk;

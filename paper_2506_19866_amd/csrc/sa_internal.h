@@ -66,6 +66,12 @@ struct DevProblem {
   // [P]: target i | source j << 7 | in-degree(i) << 14 | out-degree(j) << 21 |
   // edge << 28 | observed(i) << 29 | observed(j) << 30 (j = 0 for a threshold)
   const uint32_t *param_info;
+  // priority model (model 1, sa_priority.h): lc lanes per chain (16, 32 or 64
+  // >= N), node i on lane i of its chain's lane segment
+  int32_t model;
+  int32_t lc;
+  const uint8_t *pr_start;  // [C][lc]: state at t = 0 | 4 if held (clamped, or a lane beyond N)
+  const uint8_t *pr_obs;    // [C][T+1][lc]: reference value | W << 2 (0 where not observed)
 };
 
 // One temperature stage of one problem.
@@ -173,6 +179,11 @@ constexpr int kPersistentTilesM = 10, kPersistentTilesK = 2;  // networks up to 
 constexpr int kPersistentClasses = 3;
 constexpr int kPersistentQueues = 2 * kPersistentClasses;     // one work counter per (class, step size)
 int launch_learned_stage(const DevProblem &pb, const StageArgs &sa, const LearnedArgs &la, void *stream);
+// Priority model (sa_k_priority.hip): cost, trajectories and one stage.
+int launch_priority_eval(const DevProblem &pb, const int8_t *x, int64_t n, int32_t *cost, void *stream);
+int launch_priority_simulate(const DevProblem &pb, const int8_t *x, int64_t n, int8_t *traj, void *stream);
+int launch_priority_stage(const DevProblem &pb, const StageArgs &sa, void *stream);
+size_t priority_stage_smem_bytes(const DevProblem &pb);
 // LDS of a learned-stage workgroup; prepare sets the kernel's LDS limit to it.
 size_t learned_smem_bytes(const DevProblem &pb, bool model);
 int learned_stage_prepare(const DevProblem &pb, size_t smem);

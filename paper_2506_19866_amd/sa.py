@@ -18,6 +18,7 @@ SA_OK = 0
 SA_ERR_ARG, SA_ERR_DOMAIN, SA_ERR_TOPOLOGY, SA_ERR_INFEASIBLE = -1, -2, -3, -4
 SA_ERR_DEVICE, SA_ERR_OOM, SA_ERR_UNSUPPORTED, SA_ERR_OVERFLOW = -5, -6, -7, -8
 SA_HARD, SA_PENALTY = 0, 1
+SA_MODEL_SYNCHRONOUS, SA_MODEL_PRIORITY = 0, 1
 SA_KERNEL_AUTO, SA_KERNEL_PERSISTENT = 0, 1
 SA_PROPOSAL_PLAIN, SA_PROPOSAL_LEARNED = 0, 1
 SA_SOURCE_PLAIN, SA_SOURCE_LEARNED, SA_SOURCE_STALE, SA_SOURCE_EMPTY = 0, 1, 2, 3
@@ -51,6 +52,7 @@ class _ProblemDesc(C.Structure):
         ("n_obs_nodes", C.c_int32), ("obs_nodes", C.c_void_p),
         ("observed", C.c_void_p),
         ("step_size", C.c_int32), ("constraint_mode", C.c_int32), ("penalty", C.c_int32),
+        ("model", C.c_int32),
     ]
 
 
@@ -171,7 +173,7 @@ class Problem:
             a["src"].ctypes.data if len(a["src"]) else None,
             int(prob["n_cond"]), a["init"].ctypes.data, a["clamp"].ctypes.data, int(prob["n_steps"]),
             len(a["obs_t"]), a["obs_t"].ctypes.data, len(a["obs_n"]), a["obs_n"].ctypes.data,
-            a["observed"].ctypes.data, int(prob.get("step_size", 1)), mode, lam)
+            a["observed"].ctypes.data, int(prob.get("step_size", 1)), mode, lam, int(prob.get("model", 0)))
         h = C.c_void_p()
         _check(lib().sa_create_problem(C.byref(d), C.byref(h)))
         self._h = h

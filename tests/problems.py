@@ -65,3 +65,28 @@ def random_problem(seed, *, n_nodes, n_edges, n_cond, n_steps, n_times, n_obs, n
     clean = traj[:, obs_t, :][:, :, obs_n].astype(np.int8)
     prob["observed"] = synth.add_noise(rng, clean, noise) if noise > 0 else clean
     return prob, hidden
+
+
+def priority_problem(seed, *, n_nodes, n_edges, n_cond, n_steps, n_obs, obs_t=None, noise=0.0, clamps=(0, 0),
+                     hard=1, topology="cycle_plus_uniform"):
+    """A seeded random problem of the priority-update model whose reference
+    data are the oracle trajectories of a hidden feasible vector (every time
+    point observed unless obs_t is given).  Returns (prob, hidden)."""
+    from oracle.oracle import OracleProblem
+    rng = synth.rng_for(seed)
+    if topology == "cycle_plus_uniform":
+        row_ptr, src = synth.topology_cycle_plus_uniform(rng, n_nodes, n_edges)
+    else:
+        row_ptr, src = synth.topology_bounded_indegree(rng, n_nodes, n_edges)
+    hidden = synth.priority_feasible_params(rng, 1, row_ptr, src)[0]
+    init, clamp = synth.conditions(rng, n_nodes, n_cond, clamps)
+    obs_t = np.arange(n_steps + 1, dtype=np.int32) if obs_t is None else np.asarray(obs_t, dtype=np.int32)
+    obs_n = np.sort(rng.choice(n_nodes, size=n_obs, replace=False)).astype(np.int32)
+    prob = dict(n_nodes=n_nodes, n_edges=n_edges, row_ptr=row_ptr, src=src, n_cond=n_cond,
+                init=init, clamp=clamp, n_steps=n_steps, obs_t=obs_t, obs_n=obs_n,
+                observed=np.zeros((n_cond, len(obs_t), n_obs), dtype=np.int8),
+                step_size=1, hard=hard, penalty=0, model=synth.MODEL_PRIORITY)
+    traj = OracleProblem(prob).simulate(hidden)
+    clean = traj[:, obs_t, :][:, :, obs_n].astype(np.int8)
+    prob["observed"] = synth.add_noise(rng, clean, noise) if noise > 0 else clean
+    return prob, hidden

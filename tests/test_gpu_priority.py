@@ -1,0 +1,178 @@
+"""GPU parity of the priority-update model (paper §2.1 image with weight,
+polarity and threshold; §2.2 priority update; §2.5.3; Table 1) against the
+CPU oracle, bit for bit: costs, trajectories, per-stage statistics, winners
+and best vectors.  Covers the three lane-segment widths (16, 32 and 64 lanes
+per chain), ragged chain counts, several conditions, clamps, penalty mode,
+island restart and resume."""
+import numpy as np
+import pytest
+
+from oracle.oracle import OracleProblem
+from paper_2506_19866_amd import synth
+from tests.problems import priority_problem
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2506_19866_amd import sa
+    sa.lib()
+
+
+def _sa():
+    from paper_2506_19866_amd import sa
+    return sa
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.int8)).cuda()
+
+
+# (N, E, C, T, O, clamps): segment widths 16 (N <= 16), 32 and 64
+SHAPES = [
+    (5, 9, 1, 6, 3, (0, 0)),
+    (16, 40, 3, 12, 8, (1, 1)),
+    (17, 50, 2, 9, 6, (1, 2)),
+    (32, 90, 5, 15, 20, (1, 1)),
+    (33, 100, 1, 19, 20, (0, 0)),
+    (64, 200, 4, 11, 30, (1, 3)),
+]
+
+
+def _vectors(prob, n, seed):
+    rng = synth.rng_for(seed)
+    xs = synth.priority_random_params(rng, n, prob["n_edges"], prob["n_nodes"])
+    feas = synth.priority_feasible_params(rng, n, prob["row_ptr"], prob["src"])
+    return np.concatenate([xs, feas])
+
+
+@pytest.mark.parametrize("N,E,C,T,O,clamps", SHAPES)
+@pytest.mark.parametrize("hard", [1, 0])
+def test_costs_match_oracle(N, E, C, T, O, clamps, hard):
+    prob, hidden = priority_problem(300 + N, n_nodes=N, n_edges=E, n_cond=C, n_steps=T, n_obs=O,
+                                    noise=0.1, clamps=clamps, hard=hard)
+    xs = np.concatenate([_vectors(prob, 37, N), hidden[None, :]])  # 75 vectors: ragged in every width
+    o = OracleProblem(prob)
+    want = o.cost_batch(xs)
+    P = _sa().Problem(prob)
+    assert P.n_params == 3 * (N + E)
+    got = P.eval_cost(_dev(xs)).cpu().numpy().astype(np.int64)
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("N,E,C,T,O,clamps", SHAPES)
+def test_trajectories_match_oracle(N, E, C, T, O, clamps):
+    prob, _ = priority_problem(400 + N, n_nodes=N, n_edges=E, n_cond=C, n_steps=T, n_obs=O, clamps=clamps)
+    xs = _vectors(prob, 11, 7 + N)
+    o = OracleProblem(prob)
+    got = _sa().Problem(prob).simulate(_dev(xs)).cpu().numpy()
+    for i, x in enumerate(xs):
+        assert np.array_equal(got[i], o.simulate(x)), i
+
+
+def test_sparse_observations_and_time_zero():
+    prob, _ = priority_problem(501, n_nodes=20, n_edges=60, n_cond=2, n_steps=14, n_obs=7, obs_t=[0, 5, 9, 14],
+                               noise=0.2, clamps=(1, 1))
+    xs = _vectors(prob, 20, 3)
+    assert np.array_equal(_sa().Problem(prob).eval_cost(_dev(xs)).cpu().numpy().astype(np.int64),
+                          OracleProblem(prob).cost_batch(xs))
+
+
+@pytest.mark.parametrize("name", ["q1", "q2", "q3"])
+def test_workload_costs(name):
+    w = synth.load_workload(name)
+    xs = np.concatenate([synth.start_vectors(name, w, 50), w["hidden"][None, :],
+                         synth.priority_random_params(synth.rng_for(9), 30, w["n_edges"], w["n_nodes"])])
+    got = _sa().Problem(w).eval_cost(_dev(xs)).cpu().numpy().astype(np.int64)
+    assert np.array_equal(got, OracleProblem(w).cost_batch(xs))
+
+
+def _compare_runs(prob, x0, seed, *, T0, rho, n_stages, L, first_stage=0, group_size=0, **kw):
+    o = OracleProblem(prob)
+    ref = o.run(x0, seed=seed, T0=T0, rho=rho, n_stages=n_stages, steps_per_stage=L, first_stage=first_stage,
+                n_threads=8, group_size=group_size)
+    sa = _sa()
+    run = sa.Run(sa.Problem(prob), _dev(x0), seed=seed, T0=T0, rho=rho, n_stages=n_stages, steps_per_stage=L,
+                 first_stage=first_stage, group_size=group_size, **kw)
+    st = run.stats()
+    x, cost, winner = run.best()
+    cb, cx = run.chain_best()
+    assert np.array_equal(st["best_cost"], ref["stage_best"])
+    assert np.array_equal(st["winner"], ref["stage_winner"])
+    for k in ("accepted", "uphill", "neutral", "infeasible"):
+        assert np.array_equal(st[k], ref["stage_" + k]), k
+    assert cost == ref["cost"] and winner == ref["winner"]
+    assert np.array_equal(x, ref["x"])
+    assert np.array_equal(cb.astype(np.int64), ref["chain_best"])
+    assert np.array_equal(cx, ref["chain_xbest"])
+    return ref
+
+
+def test_run_q1():
+    w = synth.load_workload("q1")
+    s = synth.bench_schedule("q1")
+    x0 = synth.start_vectors("q1", w, 21)      # 16-lane segments: 4 chains per wave, ragged
+    ref = _compare_runs(w, x0, s["seed"], T0=s["T0"], rho=s["rho"], n_stages=8, L=70)
+    assert ref["cost"] <= ref["stage_best"][0]
+
+
+def test_run_q2_truncated():
+    w = synth.load_workload("q2")
+    s = synth.bench_schedule("q2")
+    x0 = synth.start_vectors("q2", w, 70)
+    _compare_runs(w, x0, s["seed"], T0=s["T0"], rho=s["rho"], n_stages=3, L=100)
+
+
+def test_run_q3_truncated():
+    w = synth.load_workload("q3")
+    s = synth.bench_schedule("q3")
+    x0 = synth.start_vectors("q3", w, 9)
+    _compare_runs(w, x0, s["seed"], T0=s["T0"], rho=s["rho"], n_stages=2, L=40)
+
+
+@pytest.mark.parametrize("N,E,C,T,O,clamps", [SHAPES[2], SHAPES[3]])
+def test_run_other_widths_penalty_resume_islands(N, E, C, T, O, clamps):
+    prob, _ = priority_problem(600 + N, n_nodes=N, n_edges=E, n_cond=C, n_steps=T, n_obs=O, noise=0.1,
+                               clamps=clamps, hard=0)
+    x0 = synth.priority_random_params(synth.rng_for(N), 13, E, N)    # penalty mode: infeasible starts allowed
+    _compare_runs(prob, x0, 55, T0=1.5, rho=0.8, n_stages=4, L=45, first_stage=2, group_size=4)
+
+
+def test_run_hard_mode_counts_infeasible_and_graph():
+    prob, _ = priority_problem(701, n_nodes=12, n_edges=20, n_cond=2, n_steps=8, n_obs=6, noise=0.1)
+    x0 = synth.priority_feasible_params(synth.rng_for(5), 10, prob["row_ptr"], prob["src"])
+    ref = _compare_runs(prob, x0, 8, T0=2.0, rho=0.7, n_stages=3, L=50, use_graph=True)
+    assert ref["stage_infeasible"].sum() > 0
+
+
+def test_rejections():
+    sa = _sa()
+    w = synth.load_workload("q1")
+    x0 = synth.start_vectors("q1", w, 4)
+    P = sa.Problem(w)
+    kw = dict(seed=1, T0=1.0, rho=0.9, n_stages=1, steps_per_stage=4)
+    with pytest.raises(sa.SAError) as e:
+        sa.Run(P, _dev(x0), kernel=sa.SA_KERNEL_PERSISTENT, **kw)
+    assert e.value.code == sa.SA_ERR_UNSUPPORTED
+    with pytest.raises(sa.SAError) as e:
+        sa.Run([P, P], [_dev(x0), _dev(x0)], **kw)
+    assert e.value.code == sa.SA_ERR_UNSUPPORTED
+    bad = x0.copy()
+    bad[0, 3 * w["n_edges"]] = 7                     # a speed outside {1..6, 10..12}
+    with pytest.raises(sa.SAError) as e:
+        sa.Run(P, _dev(bad), **kw)
+    assert e.value.code == sa.SA_ERR_DOMAIN
+    infeasible = x0.copy()
+    infeasible[0, :w["n_edges"]] = 0                 # every weight 0
+    with pytest.raises(sa.SAError) as e:
+        sa.Run(P, _dev(infeasible), **kw)
+    assert e.value.code == sa.SA_ERR_INFEASIBLE
+    big, _ = priority_problem(801, n_nodes=65, n_edges=130, n_cond=1, n_steps=3, n_obs=5)
+    with pytest.raises(sa.SAError) as e:
+        sa.Problem(big)
+    assert e.value.code == sa.SA_ERR_UNSUPPORTED
