@@ -172,7 +172,11 @@ static int create_priority(const sa_problem_desc *d, const std::vector<int> &W, 
   const int N = d->n_nodes, E = d->n_edges, C = d->n_conditions, T = d->n_steps;
   const int K = d->n_obs_times, O = d->n_obs_nodes, P = 3 * E + 3 * N;
   const int lc = N <= 16 ? 16 : N <= 32 ? 32 : 64;
-  std::vector<uint8_t> start((size_t)C * lc), obs((size_t)C * (T + 1) * lc, 0);
+  int max_in = 0;
+  for (int i = 0; i < N; ++i) max_in = std::max(max_in, d->in_row_ptr[i + 1] - d->in_row_ptr[i]);
+  const int dmax = max_in <= 8 ? 8 : max_in <= 16 ? 16 : 0;
+  std::vector<uint8_t> start((size_t)C * lc);
+  std::vector<uint32_t> obs((size_t)C * (T + 1) * lc, 0);
   for (int c = 0; c < C; ++c)
     for (int v = 0; v < lc; ++v) {
       int val = 0, held = 1;
@@ -187,8 +191,9 @@ static int create_priority(const sa_problem_desc *d, const std::vector<int> &W, 
     for (int k = 0; k < K; ++k)
       for (int o = 0; o < O; ++o) {
         const size_t at = ((size_t)c * K + k) * O + o;
-        obs[((size_t)c * (T + 1) + d->obs_times[k]) * lc + d->obs_nodes[o]] =
-            (uint8_t)(d->observed[at] | W[at] << 2);
+        uint32_t cost = 0;
+        for (int v = 0; v < 3; ++v) cost |= (uint32_t)(W[at] * std::abs(v - d->observed[at])) << (8 * v);
+        obs[((size_t)c * (T + 1) + d->obs_times[k]) * lc + d->obs_nodes[o]] = cost;
       }
   std::vector<int32_t> esrc(E), edst(E);
   for (int i = 0; i < N; ++i)
@@ -202,7 +207,7 @@ static int create_priority(const sa_problem_desc *d, const std::vector<int> &W, 
   Layout lay;
   const size_t o_esrc = lay.take((size_t)E * 4), o_edst = lay.take((size_t)E * 4);
   const size_t o_inptr = lay.take((size_t)(N + 1) * 4);
-  const size_t o_start = lay.take(start.size()), o_obs = lay.take(obs.size());
+  const size_t o_start = lay.take(start.size()), o_obs = lay.take(obs.size() * 4);
   hipError_t e = hipMalloc(&pr->dmem, lay.bytes);
   if (e != hipSuccess) {
     delete pr;
@@ -216,7 +221,7 @@ static int create_priority(const sa_problem_desc *d, const std::vector<int> &W, 
   put(o_edst, edst.data(), (size_t)E * 4);
   put(o_inptr, d->in_row_ptr, (size_t)(N + 1) * 4);
   put(o_start, start.data(), start.size());
-  put(o_obs, obs.data(), obs.size());
+  put(o_obs, obs.data(), obs.size() * 4);
   e = hipMemcpy(pr->dmem, host.data(), lay.bytes, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     hipFree(pr->dmem);
@@ -234,8 +239,9 @@ static int create_priority(const sa_problem_desc *d, const std::vector<int> &W, 
   dp.in_ptr = (const int32_t *)(base + o_inptr);
   dp.model = SA_MODEL_PRIORITY;
   dp.lc = lc;
+  dp.dmax = dmax;
   dp.pr_start = (const uint8_t *)(base + o_start);
-  dp.pr_obs = (const uint8_t *)(base + o_obs);
+  dp.pr_obs = (const uint32_t *)(base + o_obs);
 
   sa_problem_info &in = pr->info;
   in.n_params = P; in.n_nodes = N; in.n_edges = E; in.n_conditions = C; in.n_steps = T;

@@ -70,8 +70,9 @@ struct DevProblem {
   // >= N), node i on lane i of its chain's lane segment
   int32_t model;
   int32_t lc;
+  int32_t dmax;             // regulator slots per node (8 or 16, >= the largest in-degree), 0: masks
   const uint8_t *pr_start;  // [C][lc]: state at t = 0 | 4 if held (clamped, or a lane beyond N)
-  const uint8_t *pr_obs;    // [C][T+1][lc]: reference value | W << 2 (0 where not observed)
+  const uint32_t *pr_obs;   // [C][T+1][lc]: byte s = W * |s - R| for s = 0, 1, 2 (0 where not observed)
 };
 
 // One temperature stage of one problem.

@@ -24,7 +24,7 @@ struct SegPos {
   }
 };
 
-template <int LC>
+template <int LC, int DMAX>
 __global__ __launch_bounds__(kBlock) void pr_eval_kernel(DevProblem pb, const int8_t *__restrict__ x, int64_t n,
                                                          int32_t *__restrict__ cost) {
   const SegPos<LC> sp;
@@ -34,16 +34,16 @@ __global__ __launch_bounds__(kBlock) void pr_eval_kernel(DevProblem pb, const in
   const bool valid = sp.index < n;
   const int8_t *xi = x + (valid ? sp.index : n - 1) * pb.P;
   auto xv = [xi](int k) -> int { return xi[k]; };
-  PrMasks<LC> m;
-  int u, mem, d;
-  pr_build<LC>(pb, sp.li, xv, m, u, mem, d);
-  const int mis = seg_sum<LC>(pr_mismatch<LC, false>(pb, sp.li, sp.base, m, u, mem, d, pb.pr_start, pb.pr_obs,
-                                                     nullptr));
-  const int v = pr_violations<LC>(pb, sp.li, m);
+  PrNode<LC, DMAX> nd;
+  PrAddr<DMAX> ad;
+  pr_build<LC, DMAX>(pb, sp.li, sp.base, xv, nd, ad);
+  const int mis = seg_sum<LC>(pr_mismatch<LC, DMAX, false>(pb, sp.li, sp.base, nd, ad, pb.pr_start, pb.pr_obs,
+                                                           nullptr));
+  const int v = pr_violations<LC, DMAX>(pb, sp.li, nd);
   if (valid && sp.li == 0) cost[sp.index] = mis + pb.lambda * v;
 }
 
-template <int LC>
+template <int LC, int DMAX>
 __global__ __launch_bounds__(kBlock) void pr_simulate_kernel(DevProblem pb, const int8_t *__restrict__ x, int64_t n,
                                                              int8_t *__restrict__ traj) {
   const SegPos<LC> sp;
@@ -52,35 +52,34 @@ __global__ __launch_bounds__(kBlock) void pr_simulate_kernel(DevProblem pb, cons
   const int64_t i = valid ? sp.index : n - 1;
   const int8_t *xi = x + i * pb.P;
   auto xv = [xi](int k) -> int { return xi[k]; };
-  PrMasks<LC> m;
-  int u, mem, d;
-  pr_build<LC>(pb, sp.li, xv, m, u, mem, d);
-  // a segment past the last vector still takes part in the ballots, with its
-  // stores switched off
-  pr_mismatch<LC, true>(pb, sp.li, sp.base, m, u, mem, d, pb.pr_start, pb.pr_obs,
-                        valid ? traj + (size_t)i * pb.C * (pb.T + 1) * pb.N : nullptr);
+  PrNode<LC, DMAX> nd;
+  PrAddr<DMAX> ad;
+  pr_build<LC, DMAX>(pb, sp.li, sp.base, xv, nd, ad);
+  // a segment past the last vector still takes part in the lane exchanges,
+  // with its stores switched off
+  pr_mismatch<LC, DMAX, true>(pb, sp.li, sp.base, nd, ad, pb.pr_start, pb.pr_obs,
+                              valid ? traj + (size_t)i * pb.C * (pb.T + 1) * pb.N : nullptr);
 }
 
 // LDS of a chain: x_current and x_best, P rounded up to 4 bytes each.
 __host__ __device__ inline int pr_chain_bytes(const DevProblem &pb) { return 2 * round4(pb.P); }
 __host__ __device__ inline int pr_table_bytes(const DevProblem &pb) {
-  return round4(pb.C * pb.lc) + round4(pb.C * (pb.T + 1) * pb.lc);
+  return round4(pb.C * pb.lc) + 4 * pb.C * (pb.T + 1) * pb.lc;
 }
 
 // One temperature stage: per chain L steps of GetCandidate -> Simulate ->
 // score -> Metropolis (Table 1), with the priority model's domains.
-template <int LC>
+template <int LC, int DMAX>
 __global__ __launch_bounds__(kBlock) void pr_stage_kernel(DevProblem pb, StageArgs sa) {
   extern __shared__ uint32_t smem[];
   const int tb = pr_table_bytes(pb);
   uint8_t *lstart = reinterpret_cast<uint8_t *>(smem);
-  uint8_t *lobs = lstart + round4(pb.C * LC);
+  uint32_t *lobs = reinterpret_cast<uint32_t *>(lstart + round4(pb.C * LC));
   {
     const uint32_t *gs = reinterpret_cast<const uint32_t *>(pb.pr_start);
-    const uint32_t *go = reinterpret_cast<const uint32_t *>(pb.pr_obs);
-    uint32_t *ls = reinterpret_cast<uint32_t *>(lstart), *lo = reinterpret_cast<uint32_t *>(lobs);
+    uint32_t *ls = reinterpret_cast<uint32_t *>(lstart);
     for (int i = threadIdx.x; i < pb.C * LC / 4; i += kBlock) ls[i] = gs[i];
-    for (int i = threadIdx.x; i < pb.C * (pb.T + 1) * LC / 4; i += kBlock) lo[i] = go[i];
+    for (int i = threadIdx.x; i < pb.C * (pb.T + 1) * LC; i += kBlock) lobs[i] = pb.pr_obs[i];
   }
   __syncthreads();
 
@@ -99,12 +98,12 @@ __global__ __launch_bounds__(kBlock) void pr_stage_kernel(DevProblem pb, StageAr
   for (int k = li; k < P; k += LC) xcur[k] = xbst[k] = (uint8_t)xs[k];
   wave_sync();
   auto xv = [xcur](int k) -> int { return (int)(int8_t)xcur[k]; };
-  PrMasks<LC> m;
-  int u, mem, d;
-  pr_build<LC>(pb, li, xv, m, u, mem, d);
-  int vcur = pr_violations<LC>(pb, li, m);
+  PrNode<LC, DMAX> nd;
+  PrAddr<DMAX> ad;
+  pr_build<LC, DMAX>(pb, li, base, xv, nd, ad);
+  int vcur = pr_violations<LC, DMAX>(pb, li, nd);
   // Table 1: every stage starts by scoring the vector it restarts from
-  int ccur = seg_sum<LC>(pr_mismatch<LC, false>(pb, li, base, m, u, mem, d, lstart, lobs, nullptr)) +
+  int ccur = seg_sum<LC>(pr_mismatch<LC, DMAX, false>(pb, li, base, nd, ad, lstart, lobs, nullptr)) +
              pb.lambda * vcur;
   int cbest = ccur;
   uint32_t n_acc = 0, n_up = 0, n_neu = 0, n_inf = 0;
@@ -126,9 +125,8 @@ __global__ __launch_bounds__(kBlock) void pr_stage_kernel(DevProblem pb, StageAr
       int nc = pr_code(blk, old) + 1 + (int)(((uint64_t)r1 * (uint64_t)(ksz - 1)) >> 32);
       if (nc >= ksz) nc -= ksz;
       const int nv = pr_value(blk, nc);
-      // the candidate's masks and node parameters
-      PrMasks<LC> mc = m;
-      int uc = u, mc_mem = mem, dc = d;
+      // the candidate's node state: only the lane of the changed node differs
+      PrNode<LC, DMAX> cand = nd;
       if (blk < 3) {
         const int e = p - blk * E;
         const int dst = pb.edge_dst[e];
@@ -137,27 +135,27 @@ __global__ __launch_bounds__(kBlock) void pr_stage_kernel(DevProblem pb, StageAr
           if (blk == 0) w = nv;
           if (blk == 1) pol = nv;
           if (blk == 2) t = nv;
-          pr_set_edge<LC>(mc, (SegMask<LC>)1 << pb.edge_src[e], w, pol, t);
+          pr_set_edge<LC, DMAX>(cand, e - pb.in_ptr[dst], pb.edge_src[e], w, pol, t);
         }
       } else {
         const int node = p - 3 * E - (blk - 3) * N;
         if (li == node) {
-          if (blk == 3) uc = nv;
-          if (blk == 4) mc_mem = nv;
-          if (blk == 5) dc = nv;
+          if (blk == 3) cand.u = nv;
+          if (blk == 4) cand.mem = nv;
+          if (blk == 5) cand.d = nv;
         }
       }
       // V changes only with a weight or a polarity; the reduction runs in
       // wave-uniform control flow
       int vc = vcur;
       if (__builtin_amdgcn_ballot_w64(blk < 2) != 0) {
-        const int vnew = pr_violations<LC>(pb, li, mc);
+        const int vnew = pr_violations<LC, DMAX>(pb, li, cand);
         if (blk < 2) vc = vnew;
       }
       const bool feasible = !(pb.hard && vc > 0);
       int ccand = 0;
       if (__builtin_amdgcn_ballot_w64(feasible) != 0)
-        ccand = seg_sum<LC>(pr_mismatch<LC, false>(pb, li, base, mc, uc, mc_mem, dc, lstart, lobs, nullptr)) +
+        ccand = seg_sum<LC>(pr_mismatch<LC, DMAX, false>(pb, li, base, cand, ad, lstart, lobs, nullptr)) +
                 pb.lambda * vc;
       const int delta = ccand - ccur;
       // Metropolis in fixed point: accept iff delta <= 0 or u32 < tau[delta]
@@ -169,10 +167,7 @@ __global__ __launch_bounds__(kBlock) void pr_stage_kernel(DevProblem pb, StageAr
         ++n_acc;
         n_up += delta > 0;
         n_neu += delta == 0;
-        m = mc;
-        u = uc;
-        mem = mc_mem;
-        d = dc;
+        nd = cand;
         vcur = vc;
         ccur = ccand;
       }
@@ -216,12 +211,18 @@ size_t priority_stage_smem_bytes(const DevProblem &pb) {
   return (size_t)pr_table_bytes(pb) + (size_t)(kBlock / kWave) * (kWave / pb.lc) * pr_chain_bytes(pb);
 }
 
-#define SA_PR_DISPATCH(KERNEL, GRID, SMEM, ...)                                       \
-  switch (pb.lc) {                                                                   \
-    case 16: KERNEL<16><<<GRID, kBlock, SMEM, s>>>(__VA_ARGS__); break;              \
-    case 32: KERNEL<32><<<GRID, kBlock, SMEM, s>>>(__VA_ARGS__); break;              \
-    case 64: KERNEL<64><<<GRID, kBlock, SMEM, s>>>(__VA_ARGS__); break;              \
-    default: return (int)hipErrorInvalidValue;                                       \
+// (lanes per chain, regulator slots) of every instantiated kernel
+#define SA_PR_DISPATCH(KERNEL, GRID, SMEM, ...)                                               \
+  switch (pb.lc * 100 + pb.dmax) {                                                           \
+    case 1608: KERNEL<16, 8><<<GRID, kBlock, SMEM, s>>>(__VA_ARGS__); break;                 \
+    case 1616: KERNEL<16, 16><<<GRID, kBlock, SMEM, s>>>(__VA_ARGS__); break;                \
+    case 3208: KERNEL<32, 8><<<GRID, kBlock, SMEM, s>>>(__VA_ARGS__); break;                 \
+    case 3216: KERNEL<32, 16><<<GRID, kBlock, SMEM, s>>>(__VA_ARGS__); break;                \
+    case 3200: KERNEL<32, 0><<<GRID, kBlock, SMEM, s>>>(__VA_ARGS__); break;                 \
+    case 6408: KERNEL<64, 8><<<GRID, kBlock, SMEM, s>>>(__VA_ARGS__); break;                 \
+    case 6416: KERNEL<64, 16><<<GRID, kBlock, SMEM, s>>>(__VA_ARGS__); break;                \
+    case 6400: KERNEL<64, 0><<<GRID, kBlock, SMEM, s>>>(__VA_ARGS__); break;                 \
+    default: return (int)hipErrorInvalidValue;                                               \
   }
 
 int launch_priority_eval(const DevProblem &pb, const int8_t *x, int64_t n, int32_t *cost, void *stream) {

@@ -5,19 +5,24 @@
 //
 // Layout: a chain owns a segment of LC lanes (LC = 16, 32 or 64, the smallest
 // that holds its N nodes), so a wave runs 64 / LC chains side by side; node i
-// lives on lane i of its segment.  A time step needs the states of a node's
-// regulators.  They come from two wave ballots, [s >= 1] and [s >= 2], shifted
-// to the segment: since s div 1 = [s >= 1] + [s >= 2] and s div 2 = [s >= 2],
-// the image of node i is a signed sum of population counts of those two
-// ballots under per-node regulator masks (set j belongs to a mask of node i
-// when edge j -> i has the matching threshold and product w * p):
-//   A1p/A2p/A1n/A2n: t = 1 and w*p >= 1 / = 2 / <= -1 / = -2   (against [s >= 1])
-//   B1p/B2p/B1n/B2n: any t and the same products                (against [s >= 2])
-//   K_i = |g1&A1p| + |g1&A2p| + |g2&B1p| + |g2&B2p|
-//       - |g1&A1n| - |g1&A2n| - |g2&B1n| - |g2&B2n|.
-// The highest priority of a step is a maximum over the segment (DPP within
-// rows of 16 lanes, lane shuffles across rows).  No LDS traffic per time step
-// beyond one byte of reference data.
+// lives on lane i of its segment and keeps its state, its idle and telling
+// counts and its own parameters in registers.  A time step needs the states
+// of a node's regulators, gathered in one of two ways (chosen per network):
+//
+//  * sparse (DMAX = 8 or 16 >= the largest in-degree): one slot per in-edge
+//    holding the source lane's byte address and a table of the edge's three
+//    possible contributions (s div t) * w * p for s = 0, 1, 2 as signed
+//    bytes; every lane publishes 8s, a lane-permute (ds_bpermute) fetches it
+//    from each source lane and a signed bit-field extract picks the entry;
+//  * dense (DMAX = 0): two wave ballots, [s >= 1] and [s >= 2], shifted to the
+//    segment; since s div 1 = [s >= 1] + [s >= 2] and s div 2 = [s >= 2], the
+//    image is a signed sum of population counts of those ballots under eight
+//    per-node regulator masks (threshold 1 or any, w*p >= 1, = 2, <= -1, = -2).
+//
+// The highest priority of a step is a maximum over the segment: DPP within
+// rows of 16 lanes, then gfx950's row and half-wave swaps (v_permlane16_swap,
+// v_permlane32_swap).  Two more masks per node (sources with w != 0, and
+// whether an in-edge has p = +1 and w != 0) give the constraint count.
 #pragma once
 #include "sa_device.h"
 
@@ -25,30 +30,6 @@ namespace sa {
 
 template <int LC>
 using SegMask = typename std::conditional<LC == 64, uint64_t, uint32_t>::type;
-
-// Regulator masks of one node (plus nz: sources of its in-edges with w != 0).
-template <int LC>
-struct PrMasks {
-  SegMask<LC> a1p, a2p, a1n, a2n, b1p, b2p, b1n, b2n, nz;
-};
-
-// Set or clear bit `bit` of every mask for an edge with weight w, polarity p
-// and threshold t.
-template <int LC>
-__device__ __forceinline__ void pr_set_edge(PrMasks<LC> &m, SegMask<LC> bit, int w, int p, int t) {
-  const int coef = w * p;
-  const bool t1 = t == 1;
-  auto put = [bit](SegMask<LC> &f, bool on) { f = (f & ~bit) | (on ? bit : (SegMask<LC>)0); };
-  put(m.a1p, t1 && coef >= 1);
-  put(m.a2p, t1 && coef == 2);
-  put(m.a1n, t1 && coef <= -1);
-  put(m.a2n, t1 && coef == -2);
-  put(m.b1p, coef >= 1);
-  put(m.b2p, coef == 2);
-  put(m.b1n, coef <= -1);
-  put(m.b2n, coef == -2);
-  put(m.nz, w != 0);
-}
 
 template <int LC>
 __device__ __forceinline__ int pr_popc(SegMask<LC> v) {
@@ -70,15 +51,22 @@ __device__ __forceinline__ SegMask<LC> seg_ballot(bool pred, int base) {
 
 // Maximum / sum / or over the LC lanes of the segment, in every lane of it:
 // quad_perm swaps (lanes 1,0,3,2 and 2,3,0,1) and row rotations by 4 and 8
-// give the maximum of each row of 16 lanes; shuffles across rows finish it.
+// reduce each row of 16 lanes; the row swap pairs rows 0-1 and 2-3 and the
+// half-wave swap pairs the two halves.
 template <int LC, typename Op>
 __device__ __forceinline__ int seg_reduce(int v, Op op) {
   v = op(v, __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xf, 0xf, false));   // quad_perm [1,0,3,2]
   v = op(v, __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xf, 0xf, false));   // quad_perm [2,3,0,1]
   v = op(v, __builtin_amdgcn_update_dpp(0, v, 0x124, 0xf, 0xf, false));  // row_ror:4
   v = op(v, __builtin_amdgcn_update_dpp(0, v, 0x128, 0xf, 0xf, false));  // row_ror:8
-  if constexpr (LC >= 32) v = op(v, __shfl_xor(v, 16));
-  if constexpr (LC == 64) v = op(v, __shfl_xor(v, 32));
+  if constexpr (LC >= 32) {
+    const auto r = __builtin_amdgcn_permlane16_swap((unsigned)v, (unsigned)v, false, false);
+    v = op((int)r[0], (int)r[1]);
+  }
+  if constexpr (LC == 64) {
+    const auto r = __builtin_amdgcn_permlane32_swap((unsigned)v, (unsigned)v, false, false);
+    v = op((int)r[0], (int)r[1]);
+  }
   return v;
 }
 
@@ -108,76 +96,151 @@ __device__ __forceinline__ uint32_t seg_bcast(uint32_t v, int base, int j) {
   if constexpr (LC == 64)
     return (uint32_t)__builtin_amdgcn_readlane((int)v, j);
   else
-    return (uint32_t)__shfl((int)v, base + j);
+    return (uint32_t)__builtin_amdgcn_ds_bpermute((base + j) << 2, (int)v);
 }
 
-// Masks and node parameters of this lane's node from a parameter vector
-// (xv(k) reads element k).
-template <int LC, typename XV>
-__device__ __forceinline__ void pr_build(const DevProblem &pb, int li, XV xv, PrMasks<LC> &m, int &u, int &mem,
-                                         int &d) {
-  m = PrMasks<LC>{};
-  u = mem = d = 0;
+// Contributions (s div t) * w * p of an edge for s = 0, 1, 2 as signed bytes
+// 0, 1 and 2 of a dword (byte 0 is always 0).
+__device__ __forceinline__ uint32_t pr_edge_table(int w, int p, int t) {
+  const int c = w * p;
+  const int c1 = t == 1 ? c : 0, c2 = t == 1 ? 2 * c : c;
+  return ((uint32_t)(c1 & 0xff) << 8) | ((uint32_t)(c2 & 0xff) << 16);
+}
+
+// What one lane knows about its node's regulation (the chain's current or
+// candidate parameters).
+template <int LC, int DMAX>
+struct PrNode {
+  static constexpr int kSlots = DMAX > 0 ? DMAX : 1;
+  uint32_t tab[kSlots];                           // sparse: contribution table per in-edge slot
+  SegMask<LC> a1p, a2p, a1n, a2n, b1p, b2p, b1n, b2n;  // dense: regulator masks (b1p also for V)
+  SegMask<LC> nz;                                 // sources of in-edges with w != 0
+  bool act;                                       // an in-edge with p = +1 and w != 0
+  int u, mem, d;                                  // speed, memory, step size
+};
+
+// Source lane byte addresses of the sparse slots (fixed by the topology).
+template <int DMAX>
+struct PrAddr {
+  static constexpr int kSlots = DMAX > 0 ? DMAX : 1;
+  int addr[kSlots];
+};
+
+// The slot of edge e (source j, k-th in-edge of node i) now has weight w,
+// polarity p and threshold t.
+template <int LC, int DMAX>
+__device__ __forceinline__ void pr_set_edge(PrNode<LC, DMAX> &nd, int slot, int j, int w, int p, int t) {
+  const SegMask<LC> bit = (SegMask<LC>)1 << j;
+  auto put = [bit](SegMask<LC> &f, bool on) { f = (f & ~bit) | (on ? bit : (SegMask<LC>)0); };
+  const int coef = w * p;
+  if constexpr (DMAX > 0) {
+    const uint32_t tb = pr_edge_table(w, p, t);
+#pragma unroll
+    for (int k = 0; k < DMAX; ++k) nd.tab[k] = k == slot ? tb : nd.tab[k];
+  } else {
+    const bool t1 = t == 1;
+    put(nd.a1p, t1 && coef >= 1);
+    put(nd.a2p, t1 && coef == 2);
+    put(nd.a1n, t1 && coef <= -1);
+    put(nd.a2n, t1 && coef == -2);
+    put(nd.b2p, coef == 2);
+    put(nd.b1n, coef <= -1);
+    put(nd.b2n, coef == -2);
+  }
+  put(nd.b1p, coef >= 1);
+  put(nd.nz, w != 0);
+  nd.act = nd.b1p != 0;
+}
+
+// Node state of lane li from a parameter vector (xv(k) reads element k).
+template <int LC, int DMAX, typename XV>
+__device__ __forceinline__ void pr_build(const DevProblem &pb, int li, int base, XV xv, PrNode<LC, DMAX> &nd,
+                                         PrAddr<DMAX> &ad) {
+  nd = PrNode<LC, DMAX>{};
+#pragma unroll
+  for (int k = 0; k < PrAddr<DMAX>::kSlots; ++k) ad.addr[k] = (base + li) << 2;
   if (li >= pb.N) return;
   const int E = pb.E, N = pb.N;
-  for (int e = pb.in_ptr[li]; e < pb.in_ptr[li + 1]; ++e)
-    pr_set_edge<LC>(m, (SegMask<LC>)1 << pb.edge_src[e], xv(e), xv(E + e), xv(2 * E + e));
-  u = xv(3 * E + li);
-  mem = xv(3 * E + N + li);
-  d = xv(3 * E + 2 * N + li);
+  const int e0 = pb.in_ptr[li], e1 = pb.in_ptr[li + 1];
+  for (int e = e0; e < e1; ++e) {
+    const int j = pb.edge_src[e];
+    pr_set_edge<LC, DMAX>(nd, e - e0, j, xv(e), xv(E + e), xv(2 * E + e));
+    if constexpr (DMAX > 0) {
+#pragma unroll
+      for (int k = 0; k < DMAX; ++k) ad.addr[k] = k == e - e0 ? (base + j) << 2 : ad.addr[k];
+    }
+  }
+  nd.u = xv(3 * E + li);
+  nd.mem = xv(3 * E + N + li);
+  nd.d = xv(3 * E + 2 * N + li);
 }
 
 // §2.5.3 for the segment: nodes without an in-edge with p = +1 and w != 0,
 // plus nodes without an out-edge with w != 0 (a bit of some node's nz mask).
-template <int LC>
-__device__ __forceinline__ int pr_violations(const DevProblem &pb, int li, const PrMasks<LC> &m) {
-  const SegMask<LC> sources = seg_or<LC>(m.nz);
+template <int LC, int DMAX>
+__device__ __forceinline__ int pr_violations(const DevProblem &pb, int li, const PrNode<LC, DMAX> &nd) {
+  const SegMask<LC> sources = seg_or<LC>(nd.nz);
   int v = 0;
-  if (li < pb.N) v = (m.b1p == 0) + (int)(((sources >> li) & 1) == 0);
+  if (li < pb.N) v = (int)!nd.act + (int)(((sources >> li) & 1) == 0);
   return seg_sum<LC>(v);
 }
 
+// Image K_i of this lane's node from the states s of its segment.
+template <int LC, int DMAX>
+__device__ __forceinline__ int pr_image(const PrNode<LC, DMAX> &nd, const PrAddr<DMAX> &ad, int s, int base) {
+  if constexpr (DMAX > 0) {
+    const int s8 = s << 3;
+    int img = 0;
+#pragma unroll
+    for (int k = 0; k < DMAX; k += 2) {
+      const int a = __builtin_amdgcn_ds_bpermute(ad.addr[k], s8);
+      const int b = __builtin_amdgcn_ds_bpermute(ad.addr[k + 1], s8);
+      img += __builtin_amdgcn_sbfe((int)nd.tab[k], (unsigned)a, 8u) +
+             __builtin_amdgcn_sbfe((int)nd.tab[k + 1], (unsigned)b, 8u);
+    }
+    return img;
+  } else {
+    const SegMask<LC> g1 = seg_ballot<LC>(s >= 1, base), g2 = seg_ballot<LC>(s >= 2, base);
+    return pr_popc<LC>(g1 & nd.a1p) + pr_popc<LC>(g1 & nd.a2p) + pr_popc<LC>(g2 & nd.b1p) +
+           pr_popc<LC>(g2 & nd.b2p) - pr_popc<LC>(g1 & nd.a1n) - pr_popc<LC>(g1 & nd.a2n) -
+           pr_popc<LC>(g2 & nd.b1n) - pr_popc<LC>(g2 & nd.b2n);
+  }
+}
+
 // This lane's share of the weighted mismatch of §2.3 under every condition
-// (the trajectory of §2.2's priority update); with TRAJ and a non-null traj
-// the states of every step are written to traj[(c*(T+1) + t)*N + node].
-// Every lane of the wave must call it together (ballots, reductions).
-template <int LC, bool TRAJ>
-__device__ __forceinline__ int pr_mismatch(const DevProblem &pb, int li, int base, const PrMasks<LC> &m, int u,
-                                           int mem, int d, const uint8_t *start, const uint8_t *obs,
+// (the trajectory of §2.2's priority update).  start: [C][LC] state | 4 if
+// held; obs: [C][T+1][LC] dwords whose byte s is W * |s - R| (0 where
+// nothing is observed).  With TRAJ and a non-null traj the states of every
+// step are written to traj[(c*(T+1) + t)*N + node].  Every lane of the wave
+// must call it together (ballots, lane permutes, reductions).
+template <int LC, int DMAX, bool TRAJ>
+__device__ __forceinline__ int pr_mismatch(const DevProblem &pb, int li, int base, const PrNode<LC, DMAX> &nd,
+                                           const PrAddr<DMAX> &ad, const uint8_t *start, const uint32_t *obs,
                                            int8_t *traj) {
   const int T = pb.T;
   int acc = 0;
   for (int c = 0; c < pb.C; ++c) {
     const int st = start[c * LC + li];
     int s = st & 3;
-    const bool held = (st & 4) != 0;
+    const int inc = (st & 4) ? 0 : 1;  // held nodes never count idle steps, so never get a priority
     int idle = 0, streak = 0;
-    const uint8_t *oc = obs + (size_t)c * (T + 1) * LC + li;
-    {
-      const int ob = oc[0];
-      acc += (ob >> 2) * abs(s - (ob & 3));
-    }
+    const uint32_t *oc = obs + (size_t)c * (T + 1) * LC + li;
+    acc += (int)__builtin_amdgcn_ubfe(oc[0], (unsigned)(s << 3), 8u);
     if (TRAJ && traj && li < pb.N) traj[(size_t)c * (T + 1) * pb.N + li] = (int8_t)s;
     for (int t = 1; t <= T; ++t) {
-      const SegMask<LC> g1 = seg_ballot<LC>(s >= 1, base), g2 = seg_ballot<LC>(s >= 2, base);
-      const int img = pr_popc<LC>(g1 & m.a1p) + pr_popc<LC>(g1 & m.a2p) + pr_popc<LC>(g2 & m.b1p) +
-                      pr_popc<LC>(g2 & m.b2p) - pr_popc<LC>(g1 & m.a1n) - pr_popc<LC>(g1 & m.a2n) -
-                      pr_popc<LC>(g2 & m.b1n) - pr_popc<LC>(g2 & m.b2n);
-      const int goal = img < 0 ? 0 : (img > 2 ? 2 : img);
-      const bool told = !held && goal != s;
-      idle += held ? 0 : 1;
+      const int img = pr_image<LC, DMAX>(nd, ad, s, base);
+      const int goal = min(max(img, 0), 2);
+      const bool told = inc && goal != s;
+      idle += inc;
       streak = told ? streak + 1 : 0;
-      const int prio = (told && streak > mem) ? u * idle : 0;
+      const int prio = (told && streak > nd.mem) ? nd.u * idle : 0;
       const int best = seg_max<LC>(prio);
       if (prio > 0 && prio == best) {
-        const int gap = goal - s;
-        const int step = min(abs(gap), d);
-        s += gap > 0 ? step : -step;
+        s = min(max(goal, s - nd.d), s + nd.d);  // towards the goal by at most d
         idle = 0;
         streak = 0;
       }
-      const int ob = oc[(size_t)t * LC];
-      acc += (ob >> 2) * abs(s - (ob & 3));
+      acc += (int)__builtin_amdgcn_ubfe(oc[(size_t)t * LC], (unsigned)(s << 3), 8u);
       if (TRAJ && traj && li < pb.N) traj[((size_t)c * (T + 1) + t) * pb.N + li] = (int8_t)s;
     }
   }

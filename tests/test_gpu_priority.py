@@ -33,15 +33,34 @@ def _dev(x):
     return torch.from_numpy(np.ascontiguousarray(x, dtype=np.int8)).cuda()
 
 
-# (N, E, C, T, O, clamps): segment widths 16 (N <= 16), 32 and 64
+# (N, E, C, T, O, clamps): segment widths 16 (N <= 16), 32 and 64, each with
+# 8 regulator slots, 16 slots (largest in-degree 9-16) and, for 32 and 64
+# lanes, the ballot masks (largest in-degree above 16)
 SHAPES = [
     (5, 9, 1, 6, 3, (0, 0)),
     (16, 40, 3, 12, 8, (1, 1)),
+    (12, 100, 2, 8, 6, (1, 1)),
     (17, 50, 2, 9, 6, (1, 2)),
     (32, 90, 5, 15, 20, (1, 1)),
+    (28, 300, 2, 10, 10, (1, 1)),
+    (30, 560, 1, 7, 12, (0, 0)),
     (33, 100, 1, 19, 20, (0, 0)),
     (64, 200, 4, 11, 30, (1, 3)),
+    (45, 420, 2, 9, 20, (1, 2)),
+    (48, 600, 1, 8, 20, (1, 1)),
 ]
+
+
+def _variant(prob):
+    """(lanes per chain, regulator slots) the library picks for a network."""
+    N, max_in = prob["n_nodes"], int(np.diff(prob["row_ptr"]).max())
+    return (16 if N <= 16 else 32 if N <= 32 else 64, 8 if max_in <= 8 else 16 if max_in <= 16 else 0)
+
+
+def test_shapes_cover_every_kernel_variant():
+    got = {_variant(priority_problem(300 + N, n_nodes=N, n_edges=E, n_cond=1, n_steps=2, n_obs=2)[0])
+           for N, E, *_ in SHAPES}
+    assert got == {(16, 8), (16, 16), (32, 8), (32, 16), (32, 0), (64, 8), (64, 16), (64, 0)}
 
 
 def _vectors(prob, n, seed):
@@ -67,7 +86,7 @@ def test_costs_match_oracle(N, E, C, T, O, clamps, hard):
 
 @pytest.mark.parametrize("N,E,C,T,O,clamps", SHAPES)
 def test_trajectories_match_oracle(N, E, C, T, O, clamps):
-    prob, _ = priority_problem(400 + N, n_nodes=N, n_edges=E, n_cond=C, n_steps=T, n_obs=O, clamps=clamps)
+    prob, _ = priority_problem(300 + N, n_nodes=N, n_edges=E, n_cond=C, n_steps=T, n_obs=O, clamps=clamps)
     xs = _vectors(prob, 11, 7 + N)
     o = OracleProblem(prob)
     got = _sa().Problem(prob).simulate(_dev(xs)).cpu().numpy()
@@ -135,9 +154,9 @@ def test_run_q3_truncated():
     _compare_runs(w, x0, s["seed"], T0=s["T0"], rho=s["rho"], n_stages=2, L=40)
 
 
-@pytest.mark.parametrize("N,E,C,T,O,clamps", [SHAPES[2], SHAPES[3]])
+@pytest.mark.parametrize("N,E,C,T,O,clamps", [SHAPES[3], SHAPES[4], SHAPES[6], SHAPES[9], SHAPES[10]])
 def test_run_other_widths_penalty_resume_islands(N, E, C, T, O, clamps):
-    prob, _ = priority_problem(600 + N, n_nodes=N, n_edges=E, n_cond=C, n_steps=T, n_obs=O, noise=0.1,
+    prob, _ = priority_problem(300 + N, n_nodes=N, n_edges=E, n_cond=C, n_steps=T, n_obs=O, noise=0.1,
                                clamps=clamps, hard=0)
     x0 = synth.priority_random_params(synth.rng_for(N), 13, E, N)    # penalty mode: infeasible starts allowed
     _compare_runs(prob, x0, 55, T0=1.5, rho=0.8, n_stages=4, L=45, first_stage=2, group_size=4)
