@@ -33,18 +33,27 @@ ALU_PEAK_OPS = CU * SIMD_PER_CU * LANES * CLOCK_HZ          # 39.3e12 int32 lane
 PROFILES = os.path.join(ROOT, "profiles")
 STAGE_KERNEL_SOURCES = ("paper_2506_19866_amd/csrc/sa_k_stage.hip", "paper_2506_19866_amd/csrc/sa_chain.h",
                         "paper_2506_19866_amd/csrc/sa_device.h", "paper_2506_19866_amd/csrc/sa_internal.h")
+PRIORITY_KERNEL_SOURCES = ("paper_2506_19866_amd/csrc/sa_k_priority.hip", "paper_2506_19866_amd/csrc/sa_priority.h",
+                           "paper_2506_19866_amd/csrc/sa_device.h", "paper_2506_19866_amd/csrc/sa_internal.h")
+# committed HBM byte counts per kernel: (summary file, the sources it was taken with)
+PMC_SUMMARIES = {"stage": ("stage_kernel_c3_pmc.json", STAGE_KERNEL_SOURCES),
+                 "priority": ("pr_stage_kernel_q3_pmc.json", PRIORITY_KERNEL_SOURCES)}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def stage_kernel_hash() -> str:
+def sources_hash(sources) -> str:
     h = hashlib.sha256()
-    for rel in STAGE_KERNEL_SOURCES:
+    for rel in sources:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
+
+
+def stage_kernel_hash(kind: str = "stage") -> str:
+    return sources_hash(PMC_SUMMARIES[kind][1])
 
 
 def algorithmic_alu_ops(prob: dict) -> int:
@@ -69,15 +78,15 @@ def algorithmic_alu_ops_priority(prob: dict) -> int:
     return 2 * C * T * E + 6 * C * T * N + 2 * C * K * O
 
 
-def traffic_from_profiles(launch_key: str):
+def traffic_from_profiles(launch_key: str, kind: str = "stage"):
     """HBM bytes per stage-kernel launch from the committed PMC summary, or
     None when it is missing or the kernel sources changed since."""
-    path = os.path.join(PROFILES, "stage_kernel_c3_pmc.json")
+    path = os.path.join(PROFILES, PMC_SUMMARIES[kind][0])
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("kernel_sources_sha256_16") != stage_kernel_hash() or rec.get("launch") != launch_key:
+    if rec.get("kernel_sources_sha256_16") != stage_kernel_hash(kind) or rec.get("launch") != launch_key:
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -448,8 +457,9 @@ def main() -> int:
     launch_key = f"{name}:{n}x{L}"
     if priority:
         lc = 16 if prob["n_nodes"] <= 16 else 32 if prob["n_nodes"] <= 32 else 64
-        kernel = f"pr_stage_kernel<{lc}>"
-        traffic = None
+        max_in = int(np.diff(prob["row_ptr"]).max())
+        kernel = f"pr_stage_kernel<{lc},{8 if max_in <= 8 else 16 if max_in <= 16 else 0}>"
+        traffic = traffic_from_profiles(launch_key, "priority")
         model = (f"the paper's priority-update model, {prob['n_nodes']} nodes, {prob['n_edges']} edges, "
                  f"{P.n_params} params (w, p, t per edge; u, m, d per node)")
     else:

@@ -12,8 +12,9 @@
 //  * sparse (DMAX = 8 or 16 >= the largest in-degree): one slot per in-edge
 //    holding the source lane's byte address and a table of the edge's three
 //    possible contributions (s div t) * w * p for s = 0, 1, 2 as signed
-//    bytes; every lane publishes 8s, a lane-permute (ds_bpermute) fetches it
-//    from each source lane and a signed bit-field extract picks the entry;
+//    bytes; every lane publishes its state as a one-hot byte code, a lane
+//    permute (ds_bpermute) fetches it from each source lane and a 4-byte dot
+//    product (v_dot4_i32_i8) with the table adds the contribution;
 //  * dense (DMAX = 0): two wave ballots, [s >= 1] and [s >= 2], shifted to the
 //    segment; since s div 1 = [s >= 1] + [s >= 2] and s div 2 = [s >= 2], the
 //    image is a signed sum of population counts of those ballots under eight
@@ -185,20 +186,25 @@ __device__ __forceinline__ int pr_violations(const DevProblem &pb, int li, const
   return seg_sum<LC>(v);
 }
 
-// Image K_i of this lane's node from the states s of its segment.
+// One-hot byte code of a state: byte s of the dword is 1.
+__device__ __forceinline__ int pr_onehot(int s) { return 1 << (s << 3); }
+
+// Image K_i of this lane's node from the states of its segment (s, and its
+// one-hot code oh, in every lane): in the sparse form a lane permute fetches
+// each source's one-hot code and a 4-byte dot product with the edge's table
+// picks the contribution and accumulates it.
 template <int LC, int DMAX>
-__device__ __forceinline__ int pr_image(const PrNode<LC, DMAX> &nd, const PrAddr<DMAX> &ad, int s, int base) {
+__device__ __forceinline__ int pr_image(const PrNode<LC, DMAX> &nd, const PrAddr<DMAX> &ad, int s, int oh,
+                                        int base) {
   if constexpr (DMAX > 0) {
-    const int s8 = s << 3;
-    int img = 0;
+    int img0 = 0, img1 = 0;
 #pragma unroll
     for (int k = 0; k < DMAX; k += 2) {
-      const int a = __builtin_amdgcn_ds_bpermute(ad.addr[k], s8);
-      const int b = __builtin_amdgcn_ds_bpermute(ad.addr[k + 1], s8);
-      img += __builtin_amdgcn_sbfe((int)nd.tab[k], (unsigned)a, 8u) +
-             __builtin_amdgcn_sbfe((int)nd.tab[k + 1], (unsigned)b, 8u);
+      img0 = __builtin_amdgcn_sdot4((int)nd.tab[k], __builtin_amdgcn_ds_bpermute(ad.addr[k], oh), img0, false);
+      img1 = __builtin_amdgcn_sdot4((int)nd.tab[k + 1], __builtin_amdgcn_ds_bpermute(ad.addr[k + 1], oh), img1,
+                                    false);
     }
-    return img;
+    return img0 + img1;
   } else {
     const SegMask<LC> g1 = seg_ballot<LC>(s >= 1, base), g2 = seg_ballot<LC>(s >= 2, base);
     return pr_popc<LC>(g1 & nd.a1p) + pr_popc<LC>(g1 & nd.a2p) + pr_popc<LC>(g2 & nd.b1p) +
@@ -225,22 +231,25 @@ __device__ __forceinline__ int pr_mismatch(const DevProblem &pb, int li, int bas
     const int inc = (st & 4) ? 0 : 1;  // held nodes never count idle steps, so never get a priority
     int idle = 0, streak = 0;
     const uint32_t *oc = obs + (size_t)c * (T + 1) * LC + li;
-    acc += (int)__builtin_amdgcn_ubfe(oc[0], (unsigned)(s << 3), 8u);
+    int oh = pr_onehot(s);
+    acc = __builtin_amdgcn_sdot4((int)oc[0], oh, acc, false);  // picks W|s - R|
     if (TRAJ && traj && li < pb.N) traj[(size_t)c * (T + 1) * pb.N + li] = (int8_t)s;
     for (int t = 1; t <= T; ++t) {
-      const int img = pr_image<LC, DMAX>(nd, ad, s, base);
+      const int img = pr_image<LC, DMAX>(nd, ad, s, oh, base);
       const int goal = min(max(img, 0), 2);
       const bool told = inc && goal != s;
       idle += inc;
       streak = told ? streak + 1 : 0;
-      const int prio = (told && streak > nd.mem) ? nd.u * idle : 0;
+      // u <= 12 and idle <= T: a 24-bit product
+      const int prio = (told && streak > nd.mem) ? (int)__umul24((unsigned)nd.u, (unsigned)idle) : 0;
       const int best = seg_max<LC>(prio);
       if (prio > 0 && prio == best) {
         s = min(max(goal, s - nd.d), s + nd.d);  // towards the goal by at most d
         idle = 0;
         streak = 0;
       }
-      acc += (int)__builtin_amdgcn_ubfe(oc[(size_t)t * LC], (unsigned)(s << 3), 8u);
+      oh = pr_onehot(s);
+      acc = __builtin_amdgcn_sdot4((int)oc[(size_t)t * LC], oh, acc, false);
       if (TRAJ && traj && li < pb.N) traj[((size_t)c * (T + 1) + t) * pb.N + li] = (int8_t)s;
     }
   }
