@@ -125,37 +125,38 @@ __global__ __launch_bounds__(kBlock) void pr_stage_kernel(DevProblem pb, StageAr
       int nc = pr_code(blk, old) + 1 + (int)(((uint64_t)r1 * (uint64_t)(ksz - 1)) >> 32);
       if (nc >= ksz) nc -= ksz;
       const int nv = pr_value(blk, nc);
-      // the candidate's node state: only the lane of the changed node differs
-      PrNode<LC, DMAX> cand = nd;
+      // The candidate is applied to the lane of the changed node in place and
+      // undone below unless it is accepted (xcur keeps the current values).
+      const int e = blk < 3 ? p - blk * E : 0;
+      const int target = blk < 3 ? pb.edge_dst[e] : p - 3 * E - (blk - 3) * N;
+      const bool mine = li == target;
+      int slot = 0, src = 0;
       if (blk < 3) {
-        const int e = p - blk * E;
-        const int dst = pb.edge_dst[e];
-        if (li == dst) {
+        slot = e - pb.in_ptr[target];
+        src = pb.edge_src[e];
+        if (mine) {
           int w = xv(e), pol = xv(E + e), t = xv(2 * E + e);
           if (blk == 0) w = nv;
           if (blk == 1) pol = nv;
           if (blk == 2) t = nv;
-          pr_set_edge<LC, DMAX>(cand, e - pb.in_ptr[dst], pb.edge_src[e], w, pol, t);
+          pr_set_edge<LC, DMAX>(nd, slot, src, w, pol, t);
         }
-      } else {
-        const int node = p - 3 * E - (blk - 3) * N;
-        if (li == node) {
-          if (blk == 3) cand.u = nv;
-          if (blk == 4) cand.mem = nv;
-          if (blk == 5) cand.d = nv;
-        }
+      } else if (mine) {
+        if (blk == 3) nd.u = nv;
+        if (blk == 4) nd.mem = nv;
+        if (blk == 5) nd.d = nv;
       }
       // V changes only with a weight or a polarity; the reduction runs in
       // wave-uniform control flow
       int vc = vcur;
       if (__builtin_amdgcn_ballot_w64(blk < 2) != 0) {
-        const int vnew = pr_violations<LC, DMAX>(pb, li, cand);
+        const int vnew = pr_violations<LC, DMAX>(pb, li, nd);
         if (blk < 2) vc = vnew;
       }
       const bool feasible = !(pb.hard && vc > 0);
       int ccand = 0;
       if (__builtin_amdgcn_ballot_w64(feasible) != 0)
-        ccand = seg_sum<LC>(pr_mismatch<LC, DMAX, false>(pb, li, base, cand, ad, lstart, lobs, nullptr)) +
+        ccand = seg_sum<LC>(pr_mismatch<LC, DMAX, false>(pb, li, base, nd, ad, lstart, lobs, nullptr)) +
                 pb.lambda * vc;
       const int delta = ccand - ccur;
       // Metropolis in fixed point: accept iff delta <= 0 or u32 < tau[delta]
@@ -167,9 +168,18 @@ __global__ __launch_bounds__(kBlock) void pr_stage_kernel(DevProblem pb, StageAr
         ++n_acc;
         n_up += delta > 0;
         n_neu += delta == 0;
-        nd = cand;
         vcur = vc;
         ccur = ccand;
+      }
+      if (!accept && mine) {  // back to the current parameters
+        if (blk < 3)
+          pr_set_edge<LC, DMAX>(nd, slot, src, xv(e), xv(E + e), xv(2 * E + e));
+        else if (blk == 3)
+          nd.u = old;
+        else if (blk == 4)
+          nd.mem = old;
+        else
+          nd.d = old;
       }
       wave_sync();
       if (accept && li == 0) xcur[p] = (uint8_t)nv;

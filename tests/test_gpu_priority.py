@@ -195,3 +195,38 @@ def test_rejections():
     with pytest.raises(sa.SAError) as e:
         sa.Problem(big)
     assert e.value.code == sa.SA_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("name", ["q2", "q3"])
+def test_full_size_stages_sampled_chains(name):
+    """Two stages of the workload in the launch configuration bench.py times
+    (every chain, 500 steps per stage).  Chains are independent within a
+    stage, so sampled chains are recomputed by the oracle one by one with
+    their own Philox ids: stage 0 from their own start vectors, stage 1 from
+    the stage-0 winner the library restarted every chain from."""
+    w = synth.load_workload(name)
+    s = synth.bench_schedule(name)
+    n, L = s["n_chains"], s["steps_per_stage"]
+    x0 = synth.start_vectors(name, w, n)
+    sa = _sa()
+    P = sa.Problem(w)
+    o = OracleProblem(w)
+    kw = dict(seed=s["seed"], T0=s["T0"], rho=s["rho"], steps_per_stage=L)
+    run = sa.Run(P, _dev(x0), n_stages=2, launch=False, **kw)
+    run.launch(1)
+    cb0, cx0 = run.chain_best()
+    st0 = run.stats()
+    sample = (0, 1, 5, n // 2 + 3, n - 2, n - 1)
+    for chain in sample:
+        ref = o.run(x0[chain:chain + 1], n_stages=1, first_chain=chain, **kw)
+        assert cb0[chain] == ref["chain_best"][0], chain
+        assert np.array_equal(cx0[chain], ref["chain_xbest"][0]), chain
+    assert st0["best_cost"][0] == cb0.min() and st0["winner"][0] == int(np.argmin(cb0))
+    winner = cx0[int(np.argmin(cb0))]
+    run.launch(1)
+    cb1, cx1 = run.chain_best()
+    for chain in sample:
+        ref = o.run(winner[None, :], n_stages=1, first_stage=1, first_chain=chain, **kw)
+        assert cb1[chain] == ref["chain_best"][0], chain
+        assert np.array_equal(cx1[chain], ref["chain_xbest"][0]), chain
+    assert np.array_equal(o.cost_batch(cx1[:6]), cb1[:6].astype(np.int64))
