@@ -144,7 +144,7 @@ def bench_batch(args) -> int:
     ops = 0.0
     for i, prob in enumerate(probs):
         st = run.stats(i)
-        sims_i = float(np.mean(n * L - st["infeasible"].astype(np.float64) + n))
+        sims_i = float(np.mean(st["simulated"].astype(np.float64)))
         ops += sims_i * algorithmic_alu_ops(prob)
     avg_stage_s = elapsed / args.steps
     achieved = ops / avg_stage_s
@@ -448,9 +448,10 @@ def main() -> int:
         f"best cost {best_cost} (stage 0 best {int(stats['best_cost'][0])})")
 
     # roofline of the stage kernel: algorithmic ALU work of the simulations it
-    # ran (one per feasible proposal plus one per chain at stage start)
+    # ran (one per chain at stage start and one per feasible proposal, less the
+    # priority model's candidates that keep the current trajectory)
     per_sim = algorithmic_alu_ops_priority(prob) if priority else algorithmic_alu_ops(prob)
-    sims = (n * L - stats["infeasible"].astype(np.float64)) + n
+    sims = stats["simulated"].astype(np.float64)
     ops_per_launch = float(np.mean(sims)) * per_sim
     avg_launch_s = float(np.mean(stage_ms)) * 1e-3
     achieved = ops_per_launch / avg_launch_s
@@ -470,7 +471,9 @@ def main() -> int:
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK_OPS / 1e12, "unit": "TOP/s",
                 "frac": achieved / ALU_PEAK_OPS, "traffic": traffic, "kernel": kernel,
                 "avg_launch_ms": float(np.mean(stage_ms)),
-                "ops_per_launch": ops_per_launch}
+                "ops_per_launch": ops_per_launch,
+                "simulations_per_launch": float(np.mean(sims)),
+                "candidates_per_launch": float(n * L)}
     out = {
         "metric": "SA chain-steps/s at 723-param scale" if P.n_params == 723 else "SA chain-steps/s",
         "value": value, "unit": "chain-steps/s",

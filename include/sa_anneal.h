@@ -221,6 +221,10 @@ typedef struct {
   uint64_t uphill;           /* accepted with D > 0 */
   uint64_t neutral;          /* accepted with D = 0 */
   uint64_t infeasible;       /* hard mode: proposals rejected for breaking (a) or (b) */
+  uint64_t simulated;        /* trajectory simulations run: one per chain for its start vector and one per
+                                feasible candidate, except (priority model) candidates that provably keep the
+                                current trajectory (an edge whose (s div t) * w * p is unchanged for every s),
+                                which are scored without one */
 } sa_stage_stats;
 
 /* Creates a run over n_probs independent problems (each with desc->n_chains

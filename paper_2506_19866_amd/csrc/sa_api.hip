@@ -914,7 +914,7 @@ extern "C" int sa_run_create(sa_problem *const *probs, int32_t n_probs, const sa
   alloc((void **)&r->xbest, (size_t)xo);
   alloc((void **)&r->xwin, (size_t)wo);
   alloc((void **)&r->cbest, (size_t)(n * n_probs) * 4);
-  alloc((void **)&r->cstats, (size_t)(n * n_probs) * 16);
+  alloc((void **)&r->cstats, (size_t)(n * n_probs) * 4 * sa::kStatWords);
   alloc((void **)&r->tau, all_tau.size() * 4);
   alloc((void **)&r->queue, sa::kPersistentQueues * sizeof(uint32_t));
   alloc((void **)&r->rec, (size_t)std::max(S, 1) * n_probs * sizeof(sa::StageRecord));
@@ -1084,6 +1084,7 @@ extern "C" int sa_stats(sa_run *r, int32_t prob, sa_stage_stats *out) {
     out[i].uphill = x.uphill;
     out[i].neutral = x.neutral;
     out[i].infeasible = x.infeasible;
+    out[i].simulated = x.simulated;
   }
   return SA_OK;
 }

@@ -18,7 +18,7 @@ struct ChainJob {
   const int8_t *x_start;  // start vector [P]
   int8_t *xbest;          // best vector out [P]
   int32_t *cbest;         // best cost out
-  uint32_t *stats;        // out: accepted, uphill, neutral, infeasible
+  uint32_t *stats;        // out: kStatWords statistics
   uint64_t seed;
   uint64_t chain;         // Philox chain id (within its network)
   uint64_t net;           // Philox network id
@@ -148,6 +148,7 @@ __device__ __forceinline__ void run_chain(const DevProblem &pb, const ChainJob &
     job.stats[1] = n_up;
     job.stats[2] = n_neu;
     job.stats[3] = n_inf;
+    job.stats[4] = 1u + (uint32_t)job.L - n_inf;  // every feasible candidate is simulated
   }
 }
 

@@ -89,13 +89,17 @@ struct StageArgs {
   int64_t group;          // later stages: chains per restart group (chain c starts from winner c / group), 0: one winner
   int8_t *xbest;          // [n_chains*P] out
   int32_t *cbest;         // [n_chains] out
-  uint32_t *cstats;       // [n_chains*4] out: accepted, uphill, neutral, infeasible
+  uint32_t *cstats;       // [n_chains*kStatWords] out
 };
+
+// Per-chain statistics of a stage: accepted, uphill, neutral, infeasible
+// candidates, and the simulations run (start vector and scored candidates).
+constexpr int kStatWords = 5;
 
 struct StageRecord {
   int32_t best_cost;
   int32_t winner;
-  uint64_t accepted, uphill, neutral, infeasible;
+  uint64_t accepted, uphill, neutral, infeasible, simulated;
 };
 
 
@@ -121,7 +125,7 @@ struct BatchArgs {
   const int64_t *w_off;       // [n_probs]: byte offset of the network's winner vector
   int8_t *xbest;              // at x_off
   int32_t *cbest;             // [n_probs * n_chains]
-  uint32_t *cstats;           // [n_probs * n_chains * 4]
+  uint32_t *cstats;           // [n_probs * n_chains * kStatWords]
 };
 
 // Table 1's serial part for every network of a run (one block per network):

@@ -37,7 +37,7 @@ __global__ __launch_bounds__(512) void persistent_kernel(BatchArgs a) {
                             : a.x_start + a.w_off[net] + (a.group ? chain / a.group : 0) * pb.P;
       job.xbest = a.xbest + a.x_off[net] + chain * pb.P;
       job.cbest = a.cbest + gc;
-      job.stats = a.cstats + gc * 4;
+      job.stats = a.cstats + gc * kStatWords;
       job.seed = a.seed;
       job.chain = (uint64_t)chain;
       job.net = (uint64_t)net;
@@ -54,33 +54,29 @@ __global__ __launch_bounds__(512) void persistent_kernel(BatchArgs a) {
 
 __global__ __launch_bounds__(256) void batch_reduce_kernel(BatchReduceArgs ra) {
   __shared__ unsigned long long keys[256];
-  __shared__ unsigned long long sums[4][256];
+  __shared__ unsigned long long sums[kStatWords][256];
   const int tid = threadIdx.x;
   const int net = blockIdx.x;
   const int64_t base = (int64_t)net * ra.n_chains;
   unsigned long long best = ~0ull;
-  unsigned long long s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  unsigned long long acc[kStatWords] = {};
   for (int64_t c = tid; c < ra.n_chains; c += 256) {
     const unsigned long long key = ((unsigned long long)(uint32_t)ra.cbest[base + c] << 32) | (unsigned long long)c;
     best = key < best ? key : best;
-    const uint32_t *st = ra.cstats + (base + c) * 4;
-    s0 += st[0];
-    s1 += st[1];
-    s2 += st[2];
-    s3 += st[3];
+    const uint32_t *st = ra.cstats + (base + c) * kStatWords;
+#pragma unroll
+    for (int q = 0; q < kStatWords; ++q) acc[q] += st[q];
   }
   keys[tid] = best;
-  sums[0][tid] = s0;
-  sums[1][tid] = s1;
-  sums[2][tid] = s2;
-  sums[3][tid] = s3;
+#pragma unroll
+  for (int q = 0; q < kStatWords; ++q) sums[q][tid] = acc[q];
   __syncthreads();
   for (int half = 128; half > 0; half >>= 1) {
     if (tid < half) {
       const unsigned long long o = keys[tid + half];
       keys[tid] = o < keys[tid] ? o : keys[tid];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) sums[q][tid] += sums[q][tid + half];
+      for (int q = 0; q < kStatWords; ++q) sums[q][tid] += sums[q][tid + half];
     }
     __syncthreads();
   }
@@ -93,6 +89,7 @@ __global__ __launch_bounds__(256) void batch_reduce_kernel(BatchReduceArgs ra) {
     r->uphill = sums[1][0];
     r->neutral = sums[2][0];
     r->infeasible = sums[3][0];
+    r->simulated = sums[4][0];
     if (net == 0 && ra.queue)  // one work counter per (size class, step size) launch
       for (int q = 0; q < kPersistentQueues; ++q) ra.queue[q] = 0u;
   }

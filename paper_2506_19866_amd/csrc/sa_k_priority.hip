@@ -103,10 +103,10 @@ __global__ __launch_bounds__(kBlock) void pr_stage_kernel(DevProblem pb, StageAr
   pr_build<LC, DMAX>(pb, li, base, xv, nd, ad);
   int vcur = pr_violations<LC, DMAX>(pb, li, nd);
   // Table 1: every stage starts by scoring the vector it restarts from
-  int ccur = seg_sum<LC>(pr_mismatch<LC, DMAX, false>(pb, li, base, nd, ad, lstart, lobs, nullptr)) +
-             pb.lambda * vcur;
+  int mcur = seg_sum<LC>(pr_mismatch<LC, DMAX, false>(pb, li, base, nd, ad, lstart, lobs, nullptr));
+  int ccur = mcur + pb.lambda * vcur;
   int cbest = ccur;
-  uint32_t n_acc = 0, n_up = 0, n_neu = 0, n_inf = 0;
+  uint32_t n_acc = 0, n_up = 0, n_neu = 0, n_inf = 0, n_sim = 1;
 
   for (int it0 = 0; it0 < sa.L; it0 += LC) {
     // one Philox block per step: lane i of the segment draws step it0 + i
@@ -131,21 +131,27 @@ __global__ __launch_bounds__(kBlock) void pr_stage_kernel(DevProblem pb, StageAr
       const int target = blk < 3 ? pb.edge_dst[e] : p - 3 * E - (blk - 3) * N;
       const bool mine = li == target;
       int slot = 0, src = 0;
+      bool moves = false;  // this lane's node can behave differently under the candidate
       if (blk < 3) {
         slot = e - pb.in_ptr[target];
         src = pb.edge_src[e];
         if (mine) {
-          int w = xv(e), pol = xv(E + e), t = xv(2 * E + e);
-          if (blk == 0) w = nv;
-          if (blk == 1) pol = nv;
-          if (blk == 2) t = nv;
+          const int w0 = xv(e), p0 = xv(E + e), t0 = xv(2 * E + e);
+          const int w = blk == 0 ? nv : w0, pol = blk == 1 ? nv : p0, t = blk == 2 ? nv : t0;
           pr_set_edge<LC, DMAX>(nd, slot, src, w, pol, t);
+          // an edge whose contributions (s div t) * w * p stay the same for every
+          // s (w or p zero before and after) leaves every image unchanged
+          moves = pr_edge_table(w, pol, t) != pr_edge_table(w0, p0, t0);
         }
       } else if (mine) {
         if (blk == 3) nd.u = nv;
         if (blk == 4) nd.mem = nv;
         if (blk == 5) nd.d = nv;
+        moves = true;
       }
+      // the trajectory, and so the mismatch, is the current one unless some
+      // node of the segment can behave differently
+      const bool same_traj = seg_ballot<LC>(moves, base) == 0;
       // V changes only with a weight or a polarity; the reduction runs in
       // wave-uniform control flow
       int vc = vcur;
@@ -154,10 +160,13 @@ __global__ __launch_bounds__(kBlock) void pr_stage_kernel(DevProblem pb, StageAr
         if (blk < 2) vc = vnew;
       }
       const bool feasible = !(pb.hard && vc > 0);
-      int ccand = 0;
-      if (__builtin_amdgcn_ballot_w64(feasible) != 0)
-        ccand = seg_sum<LC>(pr_mismatch<LC, DMAX, false>(pb, li, base, nd, ad, lstart, lobs, nullptr)) +
-                pb.lambda * vc;
+      int mcand = mcur;
+      if (__builtin_amdgcn_ballot_w64(feasible && !same_traj) != 0) {
+        const int m = seg_sum<LC>(pr_mismatch<LC, DMAX, false>(pb, li, base, nd, ad, lstart, lobs, nullptr));
+        if (!same_traj) mcand = m;
+      }
+      n_sim += feasible && !same_traj;
+      const int ccand = feasible ? mcand + pb.lambda * vc : 0;
       const int delta = ccand - ccur;
       // Metropolis in fixed point: accept iff delta <= 0 or u32 < tau[delta]
       const bool accept =
@@ -169,6 +178,7 @@ __global__ __launch_bounds__(kBlock) void pr_stage_kernel(DevProblem pb, StageAr
         n_up += delta > 0;
         n_neu += delta == 0;
         vcur = vc;
+        mcur = mcand;
         ccur = ccand;
       }
       if (!accept && mine) {  // back to the current parameters
@@ -201,11 +211,12 @@ __global__ __launch_bounds__(kBlock) void pr_stage_kernel(DevProblem pb, StageAr
     for (int k = li; k < P; k += LC) xb[k] = (int8_t)xbst[k];
     if (li == 0) {
       sa.cbest[chain] = cbest;
-      uint32_t *st = sa.cstats + chain * 4;
+      uint32_t *st = sa.cstats + chain * kStatWords;
       st[0] = n_acc;
       st[1] = n_up;
       st[2] = n_neu;
       st[3] = n_inf;
+      st[4] = n_sim;
     }
   }
 }

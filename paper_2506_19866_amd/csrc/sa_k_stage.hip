@@ -26,7 +26,7 @@ __global__ __launch_bounds__(256) void stage_kernel(DevProblem pb, StageArgs sa)
   job.x_start = sa.x_start + (sa.group ? (chain / sa.group) * pb.P : chain * sa.x_start_stride);
   job.xbest = sa.xbest + chain * pb.P;
   job.cbest = sa.cbest + chain;
-  job.stats = sa.cstats + chain * 4;
+  job.stats = sa.cstats + chain * kStatWords;
   job.seed = sa.seed;
   job.chain = (uint64_t)chain;
   job.net = (uint64_t)sa.net;

@@ -46,8 +46,10 @@ __device__ __forceinline__ SegMask<LC> seg_ballot(bool pred, int base) {
   const uint64_t b = __builtin_amdgcn_ballot_w64(pred);
   if constexpr (LC == 64)
     return b;
-  else
+  else if constexpr (LC == 32)
     return (uint32_t)(b >> base);
+  else
+    return (uint32_t)(b >> base) & 0xffffu;
 }
 
 // Maximum / sum / or over the LC lanes of the segment, in every lane of it:

@@ -83,7 +83,7 @@ class _StageStats(C.Structure):
     _fields_ = [
         ("best_cost", C.c_int32), ("winner", C.c_int32),
         ("accepted", C.c_uint64), ("uphill", C.c_uint64), ("neutral", C.c_uint64),
-        ("infeasible", C.c_uint64),
+        ("infeasible", C.c_uint64), ("simulated", C.c_uint64),
     ]
 
 

@@ -39,6 +39,7 @@ def _check_against_oracle(run, probs, x0s, seed, T0, rho, S, L, first_stage=0, n
         assert np.array_equal(st["winner"], ref["stage_winner"]), p
         for k in ("accepted", "uphill", "neutral", "infeasible"):
             assert np.array_equal(st[k], ref["stage_" + k]), (p, k)
+        assert np.array_equal(st["simulated"], len(x0) * L - st["infeasible"] + len(x0)), p
         assert cost == ref["cost"] and winner == ref["winner"], p
         assert np.array_equal(x, ref["x"]), p
         assert np.array_equal(cb.astype(np.int64), ref["chain_best"]), p

@@ -156,6 +156,9 @@ def _compare_runs(prob, x0, name_seed, *, T0, rho, n_stages, L, first_stage=0, h
     assert np.array_equal(st["winner"], ref["stage_winner"])
     for k in ("accepted", "uphill", "neutral", "infeasible"):
         assert np.array_equal(st[k], ref["stage_" + k]), k
+    # every chain simulates its start vector and every feasible candidate
+    n = len(x0)
+    assert np.array_equal(st["simulated"], n * L - st["infeasible"] + n)
     assert cost == ref["cost"] and winner == ref["winner"]
     assert np.array_equal(x, ref["x"])
     assert np.array_equal(cb.astype(np.int64), ref["chain_best"])

@@ -125,6 +125,9 @@ def _compare_runs(prob, x0, seed, *, T0, rho, n_stages, L, first_stage=0, group_
     assert np.array_equal(st["winner"], ref["stage_winner"])
     for k in ("accepted", "uphill", "neutral", "infeasible"):
         assert np.array_equal(st[k], ref["stage_" + k]), k
+    # candidates that keep the trajectory are scored without a simulation
+    n = len(x0)
+    assert (st["simulated"] <= n * L - st["infeasible"] + n).all() and (st["simulated"] >= n).all()
     assert cost == ref["cost"] and winner == ref["winner"]
     assert np.array_equal(x, ref["x"])
     assert np.array_equal(cb.astype(np.int64), ref["chain_best"])
