@@ -103,7 +103,14 @@ __global__ __launch_bounds__(kBlock) void pr_stage_kernel(DevProblem pb, StageAr
   pr_build<LC, DMAX>(pb, li, base, xv, nd, ad);
   int vcur = pr_violations<LC, DMAX>(pb, li, nd);
   // Table 1: every stage starts by scoring the vector it restarts from
-  int mcur = seg_sum<LC>(pr_mismatch<LC, DMAX, false>(pb, li, base, nd, ad, lstart, lobs, nullptr));
+  // What this lane's node did in the current trajectory (kPrTold, ...),
+  // recorded only where a wave holds one chain: with several chains per wave
+  // a simulation is skipped only when all of them can skip it, which rarely
+  // pays for the bookkeeping in every time step.
+  constexpr bool kTrackActs = LC == 64;
+  uint32_t acur = kPrTold | kPrReady | kPrFar;
+  int mcur = seg_sum<LC>(pr_mismatch<LC, DMAX, false>(pb, li, base, nd, ad, lstart, lobs, nullptr,
+                                                      kTrackActs ? &acur : nullptr));
   int ccur = mcur + pb.lambda * vcur;
   int cbest = ccur;
   uint32_t n_acc = 0, n_up = 0, n_neu = 0, n_inf = 0, n_sim = 1;
@@ -130,13 +137,15 @@ __global__ __launch_bounds__(kBlock) void pr_stage_kernel(DevProblem pb, StageAr
       const int e = blk < 3 ? p - blk * E : 0;
       const int target = blk < 3 ? pb.edge_dst[e] : p - 3 * E - (blk - 3) * N;
       const bool mine = li == target;
-      int slot = 0, src = 0;
+      int slot = 0, src = 0, w0 = 0, p0 = 0, t0 = 0;
       bool moves = false;  // this lane's node can behave differently under the candidate
       if (blk < 3) {
         slot = e - pb.in_ptr[target];
         src = pb.edge_src[e];
         if (mine) {
-          const int w0 = xv(e), p0 = xv(E + e), t0 = xv(2 * E + e);
+          w0 = xv(e);
+          p0 = xv(E + e);
+          t0 = xv(2 * E + e);
           const int w = blk == 0 ? nv : w0, pol = blk == 1 ? nv : p0, t = blk == 2 ? nv : t0;
           pr_set_edge<LC, DMAX>(nd, slot, src, w, pol, t);
           // an edge whose contributions (s div t) * w * p stay the same for every
@@ -144,10 +153,13 @@ __global__ __launch_bounds__(kBlock) void pr_stage_kernel(DevProblem pb, StageAr
           moves = pr_edge_table(w, pol, t) != pr_edge_table(w0, p0, t0);
         }
       } else if (mine) {
+        // a node never eligible ignores its speed, one never told its memory
+        // (and speed and step size), one never two levels from a goal it
+        // moved to its step size
         if (blk == 3) nd.u = nv;
         if (blk == 4) nd.mem = nv;
         if (blk == 5) nd.d = nv;
-        moves = true;
+        moves = (acur & (blk == 3 ? kPrReady : blk == 4 ? kPrTold : kPrFar)) != 0;
       }
       // the trajectory, and so the mismatch, is the current one unless some
       // node of the segment can behave differently
@@ -161,9 +173,15 @@ __global__ __launch_bounds__(kBlock) void pr_stage_kernel(DevProblem pb, StageAr
       }
       const bool feasible = !(pb.hard && vc > 0);
       int mcand = mcur;
+      uint32_t acand = acur;
       if (__builtin_amdgcn_ballot_w64(feasible && !same_traj) != 0) {
-        const int m = seg_sum<LC>(pr_mismatch<LC, DMAX, false>(pb, li, base, nd, ad, lstart, lobs, nullptr));
-        if (!same_traj) mcand = m;
+        uint32_t a = acur;
+        const int m = seg_sum<LC>(
+            pr_mismatch<LC, DMAX, false>(pb, li, base, nd, ad, lstart, lobs, nullptr, kTrackActs ? &a : nullptr));
+        if (!same_traj) {
+          mcand = m;
+          acand = a;
+        }
       }
       n_sim += feasible && !same_traj;
       const int ccand = feasible ? mcand + pb.lambda * vc : 0;
@@ -179,11 +197,12 @@ __global__ __launch_bounds__(kBlock) void pr_stage_kernel(DevProblem pb, StageAr
         n_neu += delta == 0;
         vcur = vc;
         mcur = mcand;
+        acur = acand;
         ccur = ccand;
       }
       if (!accept && mine) {  // back to the current parameters
         if (blk < 3)
-          pr_set_edge<LC, DMAX>(nd, slot, src, xv(e), xv(E + e), xv(2 * E + e));
+          pr_set_edge<LC, DMAX>(nd, slot, src, w0, p0, t0);
         else if (blk == 3)
           nd.u = old;
         else if (blk == 4)

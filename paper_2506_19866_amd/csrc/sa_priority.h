@@ -221,12 +221,19 @@ __device__ __forceinline__ int pr_image(const PrNode<LC, DMAX> &nd, const PrAddr
 // nothing is observed).  With TRAJ and a non-null traj the states of every
 // step are written to traj[(c*(T+1) + t)*N + node].  Every lane of the wave
 // must call it together (ballots, lane permutes, reductions).
+// act records, over all conditions and steps, whether the lane's node was
+// ever told to change (bit 0), ever eligible (bit 1) and ever moved towards a
+// goal two levels away (bit 2): its memory, speed and step size can only
+// matter where these happen.
+constexpr uint32_t kPrTold = 1, kPrReady = 2, kPrFar = 4;
+
 template <int LC, int DMAX, bool TRAJ>
 __device__ __forceinline__ int pr_mismatch(const DevProblem &pb, int li, int base, const PrNode<LC, DMAX> &nd,
                                            const PrAddr<DMAX> &ad, const uint8_t *start, const uint32_t *obs,
-                                           int8_t *traj) {
+                                           int8_t *traj, uint32_t *act = nullptr) {
   const int T = pb.T;
   int acc = 0;
+  bool told_any = false, ready_any = false, far_any = false;
   for (int c = 0; c < pb.C; ++c) {
     const int st = start[c * LC + li];
     int s = st & 3;
@@ -245,7 +252,10 @@ __device__ __forceinline__ int pr_mismatch(const DevProblem &pb, int li, int bas
       // u <= 12 and idle <= T: a 24-bit product
       const int prio = (told && streak > nd.mem) ? (int)__umul24((unsigned)nd.u, (unsigned)idle) : 0;
       const int best = seg_max<LC>(prio);
+      told_any |= told;
+      ready_any |= prio > 0;
       if (prio > 0 && prio == best) {
+        far_any |= abs(goal - s) == 2;
         s = min(max(goal, s - nd.d), s + nd.d);  // towards the goal by at most d
         idle = 0;
         streak = 0;
@@ -255,6 +265,7 @@ __device__ __forceinline__ int pr_mismatch(const DevProblem &pb, int li, int bas
       if (TRAJ && traj && li < pb.N) traj[((size_t)c * (T + 1) + t) * pb.N + li] = (int8_t)s;
     }
   }
+  if (act) *act = (told_any ? kPrTold : 0u) | (ready_any ? kPrReady : 0u) | (far_any ? kPrFar : 0u);
   return acc;
 }
 
