@@ -108,7 +108,7 @@ __global__ __launch_bounds__(kBlock) void pr_stage_kernel(DevProblem pb, StageAr
   // a simulation is skipped only when all of them can skip it, which rarely
   // pays for the bookkeeping in every time step.
   constexpr bool kTrackActs = LC == 64;
-  uint32_t acur = kPrTold | kPrReady | kPrFar;
+  uint32_t acur = kPrTold | kPrReady | kPrFar | kPrVisited;
   int mcur = seg_sum<LC>(pr_mismatch<LC, DMAX, false>(pb, li, base, nd, ad, lstart, lobs, nullptr,
                                                       kTrackActs ? &acur : nullptr));
   int ccur = mcur + pb.lambda * vcur;
@@ -142,15 +142,21 @@ __global__ __launch_bounds__(kBlock) void pr_stage_kernel(DevProblem pb, StageAr
       if (blk < 3) {
         slot = e - pb.in_ptr[target];
         src = pb.edge_src[e];
+        // states the source took in the current trajectory (one chain per
+        // wave: src is the same in every lane)
+        uint32_t seen = kPrVisited;
+        if constexpr (kTrackActs) seen = (uint32_t)__builtin_amdgcn_readlane((int)acur, uniform(src));
         if (mine) {
           w0 = xv(e);
           p0 = xv(E + e);
           t0 = xv(2 * E + e);
           const int w = blk == 0 ? nv : w0, pol = blk == 1 ? nv : p0, t = blk == 2 ? nv : t0;
           pr_set_edge<LC, DMAX>(nd, slot, src, w, pol, t);
-          // an edge whose contributions (s div t) * w * p stay the same for every
-          // s (w or p zero before and after) leaves every image unchanged
-          moves = pr_edge_table(w, pol, t) != pr_edge_table(w0, p0, t0);
+          // an edge whose contribution (s div t) * w * p stays the same for
+          // every state its source takes (w or p zero before and after, or a
+          // source that never leaves 0) leaves every image unchanged
+          const uint32_t diff = pr_edge_table(w, pol, t) ^ pr_edge_table(w0, p0, t0);
+          moves = ((diff & 0x0000ff00u) && (seen & 0x00000100u)) || ((diff & 0x00ff0000u) && (seen & 0x00010000u));
         }
       } else if (mine) {
         // a node never eligible ignores its speed, one never told its memory

@@ -223,9 +223,10 @@ __device__ __forceinline__ int pr_image(const PrNode<LC, DMAX> &nd, const PrAddr
 // must call it together (ballots, lane permutes, reductions).
 // act records, over all conditions and steps, whether the lane's node was
 // ever told to change (bit 0), ever eligible (bit 1) and ever moved towards a
-// goal two levels away (bit 2): its memory, speed and step size can only
-// matter where these happen.
-constexpr uint32_t kPrTold = 1, kPrReady = 2, kPrFar = 4;
+// goal two levels away (bit 2) -- its memory, speed and step size can only
+// matter where these happen -- and whether it ever held the state 1 (bit 8)
+// or 2 (bit 16), the only states in which its out-edges contribute.
+constexpr uint32_t kPrTold = 1, kPrReady = 2, kPrFar = 4, kPrVisited = 0x10100u;
 
 template <int LC, int DMAX, bool TRAJ>
 __device__ __forceinline__ int pr_mismatch(const DevProblem &pb, int li, int base, const PrNode<LC, DMAX> &nd,
@@ -234,6 +235,7 @@ __device__ __forceinline__ int pr_mismatch(const DevProblem &pb, int li, int bas
   const int T = pb.T;
   int acc = 0;
   bool told_any = false, ready_any = false, far_any = false;
+  int vis = 0;
   for (int c = 0; c < pb.C; ++c) {
     const int st = start[c * LC + li];
     int s = st & 3;
@@ -241,6 +243,7 @@ __device__ __forceinline__ int pr_mismatch(const DevProblem &pb, int li, int bas
     int idle = 0, streak = 0;
     const uint32_t *oc = obs + (size_t)c * (T + 1) * LC + li;
     int oh = pr_onehot(s);
+    vis |= oh;
     acc = __builtin_amdgcn_sdot4((int)oc[0], oh, acc, false);  // picks W|s - R|
     if (TRAJ && traj && li < pb.N) traj[(size_t)c * (T + 1) * pb.N + li] = (int8_t)s;
     for (int t = 1; t <= T; ++t) {
@@ -261,11 +264,14 @@ __device__ __forceinline__ int pr_mismatch(const DevProblem &pb, int li, int bas
         streak = 0;
       }
       oh = pr_onehot(s);
+      vis |= oh;
       acc = __builtin_amdgcn_sdot4((int)oc[(size_t)t * LC], oh, acc, false);
       if (TRAJ && traj && li < pb.N) traj[((size_t)c * (T + 1) + t) * pb.N + li] = (int8_t)s;
     }
   }
-  if (act) *act = (told_any ? kPrTold : 0u) | (ready_any ? kPrReady : 0u) | (far_any ? kPrFar : 0u);
+  if (act)
+    *act = (told_any ? kPrTold : 0u) | (ready_any ? kPrReady : 0u) | (far_any ? kPrFar : 0u) |
+           ((uint32_t)vis & kPrVisited);
   return acc;
 }
 
