@@ -43,7 +43,7 @@ def _desc(prob, **over):
         obs_n=np.ascontiguousarray(prob["obs_n"], dtype=np.int32),
         observed=np.ascontiguousarray(prob["observed"], dtype=np.int8).reshape(-1))
     scal = dict(n_nodes=prob["n_nodes"], n_edges=prob["n_edges"], n_cond=prob["n_cond"],
-                n_steps=prob["n_steps"], step_size=1, mode=sa.SA_HARD, penalty=0)
+                n_steps=prob["n_steps"], step_size=1, mode=sa.SA_HARD, penalty=0, model=0)
     for k, v in over.items():
         if k in a:
             a[k] = v
@@ -53,7 +53,7 @@ def _desc(prob, **over):
         scal["n_nodes"], scal["n_edges"], a["row_ptr"].ctypes.data, a["src"].ctypes.data,
         scal["n_cond"], a["init"].ctypes.data, a["clamp"].ctypes.data, scal["n_steps"],
         len(a["obs_t"]), a["obs_t"].ctypes.data, len(a["obs_n"]), a["obs_n"].ctypes.data,
-        a["observed"].ctypes.data, scal["step_size"], scal["mode"], scal["penalty"])
+        a["observed"].ctypes.data, scal["step_size"], scal["mode"], scal["penalty"], scal["model"])
     return d, a
 
 
@@ -88,6 +88,8 @@ def test_null_arguments(c1):
     (dict(step_size=3), sa.SA_ERR_DOMAIN),
     (dict(mode=7), sa.SA_ERR_ARG),
     (dict(penalty=-1), sa.SA_ERR_DOMAIN),
+    (dict(model=2), sa.SA_ERR_ARG),
+    (dict(model=-1), sa.SA_ERR_ARG),
 ])
 def test_scalar_validation(c1, over, code):
     rc, msg = _create(c1, **over)
@@ -146,6 +148,16 @@ def test_unsupported_sizes():
                 obs_t=np.array([1], np.int32), obs_n=np.array([0], np.int32),
                 observed=np.zeros((1, 1, 1), np.int8))
     assert _create(prob)[0] == sa.SA_ERR_UNSUPPORTED
+    # the priority-update model keeps a chain's nodes on the lanes of one wave
+    for N in (65, 200):
+        row_ptr = np.arange(N + 1, dtype=np.int32)
+        src = np.array([(i + 1) % N for i in range(N)], dtype=np.int32)
+        prob = dict(n_nodes=N, n_edges=N, row_ptr=row_ptr, src=src, n_cond=1,
+                    init=np.zeros((1, N), np.int8), clamp=np.full((1, N), -1, np.int8), n_steps=2,
+                    obs_t=np.array([1], np.int32), obs_n=np.array([0], np.int32),
+                    observed=np.zeros((1, 1, 1), np.int8))
+        rc, msg = _create(prob, model=sa.SA_MODEL_PRIORITY)
+        assert rc == sa.SA_ERR_UNSUPPORTED and "priority" in msg
 
 
 def test_mlp_rejects_bad_params_before_touching_a_device():
