@@ -321,20 +321,29 @@ def bench_learned_cost(args) -> int:
     return 0
 
 
+# default target costs of the sweep per workload
+SWEEP_TARGETS = {"c1": [10, 5, 0], "c2": [400, 350, 300], "c3": [1400, 1350, 1300], "q1": [5, 0],
+                 "q2": [60, 50, 44], "q3": [20, 10, 5, 0]}
+
+
 def bench_sweep(args) -> int:
     """Chain-count sweep over the thread counts of the paper's Table 2 (32,
-    256, 1024, 10240, 102400) on the full c3 schedule, with Table 1's global
-    restart and with the island restart in groups of --group chains (the
-    reduction suggested in §4).  One JSON line per configuration: throughput,
-    stage-kernel time of the schedule, final best cost and the stage-kernel
-    time until the global best first reaches each target cost."""
+    256, 1024, 10240, 102400) on the full schedule of --workload (c3 by
+    default; q3 is the paper's own model at the Mtb network's size), with
+    Table 1's global restart and with the island restart in groups of --group
+    chains (the reduction suggested in §4).  One JSON line per configuration:
+    throughput, stage-kernel time of the schedule, final best cost and the
+    stage-kernel time until the global best first reaches each target cost."""
     import torch
     from paper_2506_19866_amd import sa, synth
-    prob, s = synth.load_workload("c3"), synth.bench_schedule("c3")
+    name = args.workload if args.workload != "c4" else "c3"
+    if args.targets is None:
+        args.targets = SWEEP_TARGETS[name]
+    prob, s = synth.load_workload(name), synth.bench_schedule(name)
     L, S = s["steps_per_stage"], s["n_stages"]
     P = sa.Problem(prob)
     for n in args.chain_list:
-        x0 = torch.from_numpy(synth.start_vectors("c3", prob, n)).cuda()
+        x0 = torch.from_numpy(synth.start_vectors(name, prob, n)).cuda()
         for group in (0, args.group):
             if group and group >= n:
                 continue
@@ -348,7 +357,7 @@ def bench_sweep(args) -> int:
             for target in args.targets:
                 hit = np.nonzero(best <= target)[0]
                 reach[str(target)] = float(t[hit[0]]) if hit.size else None
-            out = {"chains": n, "restart": f"island {group}" if group else "global", "stages": S,
+            out = {"workload": name, "chains": n, "restart": f"island {group}" if group else "global", "stages": S,
                    "chain_steps_per_s": n * L * S / float(t[-1]), "schedule_stage_kernel_s": float(t[-1]),
                    "final_best": int(best[-1]), "time_to_target_s": reach}
             log(f"[sweep] {out}")
@@ -373,7 +382,8 @@ def main() -> int:
                          "sweep: chain counts of the paper's Table 2 with global and island restarts on c3")
     ap.add_argument("--chain-list", type=int, nargs="+", default=[32, 256, 1024, 10240, 102400])
     ap.add_argument("--group", type=int, default=32, help="sweep: chains per island restart group")
-    ap.add_argument("--targets", type=int, nargs="+", default=[1400, 1350, 1300])
+    ap.add_argument("--targets", type=int, nargs="+", default=None,
+                    help="sweep: target costs (default per workload)")
     ap.add_argument("--refresh-list", type=int, nargs="+", default=[16, 64, 256])
     ap.add_argument("--trace-rows", type=int, default=1 << 20)
     ap.add_argument("--trace-workload", default="c2", choices=["c1", "c2", "c3"])
