@@ -469,7 +469,7 @@ def main() -> int:
     if priority:
         lc = 16 if prob["n_nodes"] <= 16 else 32 if prob["n_nodes"] <= 32 else 64
         max_in = int(np.diff(prob["row_ptr"]).max())
-        kernel = f"pr_stage_kernel<{lc},{8 if max_in <= 8 else 16 if max_in <= 16 else 0}>"
+        kernel = f"pr_stage_kernel<{lc},{0 if lc <= 32 else 8 if max_in <= 8 else 16 if max_in <= 16 else 0}>"
         traffic = traffic_from_profiles(launch_key, "priority")
         model = (f"the paper's priority-update model, {prob['n_nodes']} nodes, {prob['n_edges']} edges, "
                  f"{P.n_params} params (w, p, t per edge; u, m, d per node)")

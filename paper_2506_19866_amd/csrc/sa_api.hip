@@ -174,7 +174,11 @@ static int create_priority(const sa_problem_desc *d, const std::vector<int> &W, 
   const int lc = N <= 16 ? 16 : N <= 32 ? 32 : 64;
   int max_in = 0;
   for (int i = 0; i < N; ++i) max_in = std::max(max_in, d->in_row_ptr[i + 1] - d->in_row_ptr[i]);
-  const int dmax = max_in <= 8 ? 8 : max_in <= 16 ? 16 : 0;
+  // 16- and 32-lane segments (several chains per wave) gather regulator
+  // states by ballots, which keep lane permutes off the time step's critical
+  // path; one chain per wave takes the per-slot tables unless a node has more
+  // than 16 in-edges
+  const int dmax = lc <= 32 ? 0 : max_in <= 8 ? 8 : max_in <= 16 ? 16 : 0;
   std::vector<uint8_t> start((size_t)C * lc);
   std::vector<uint32_t> obs((size_t)C * (T + 1) * lc, 0);
   for (int c = 0; c < C; ++c)

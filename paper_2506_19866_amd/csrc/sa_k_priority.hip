@@ -260,10 +260,7 @@ size_t priority_stage_smem_bytes(const DevProblem &pb) {
 // (lanes per chain, regulator slots) of every instantiated kernel
 #define SA_PR_DISPATCH(KERNEL, GRID, SMEM, ...)                                               \
   switch (pb.lc * 100 + pb.dmax) {                                                           \
-    case 1608: KERNEL<16, 8><<<GRID, kBlock, SMEM, s>>>(__VA_ARGS__); break;                 \
-    case 1616: KERNEL<16, 16><<<GRID, kBlock, SMEM, s>>>(__VA_ARGS__); break;                \
-    case 3208: KERNEL<32, 8><<<GRID, kBlock, SMEM, s>>>(__VA_ARGS__); break;                 \
-    case 3216: KERNEL<32, 16><<<GRID, kBlock, SMEM, s>>>(__VA_ARGS__); break;                \
+    case 1600: KERNEL<16, 0><<<GRID, kBlock, SMEM, s>>>(__VA_ARGS__); break;                 \
     case 3200: KERNEL<32, 0><<<GRID, kBlock, SMEM, s>>>(__VA_ARGS__); break;                 \
     case 6408: KERNEL<64, 8><<<GRID, kBlock, SMEM, s>>>(__VA_ARGS__); break;                 \
     case 6416: KERNEL<64, 16><<<GRID, kBlock, SMEM, s>>>(__VA_ARGS__); break;                \

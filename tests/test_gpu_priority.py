@@ -33,9 +33,9 @@ def _dev(x):
     return torch.from_numpy(np.ascontiguousarray(x, dtype=np.int8)).cuda()
 
 
-# (N, E, C, T, O, clamps): segment widths 16 (N <= 16), 32 and 64, each with
-# 8 regulator slots, 16 slots (largest in-degree 9-16) and, for 32 and 64
-# lanes, the ballot masks (largest in-degree above 16)
+# (N, E, C, T, O, clamps): segment widths 16 (N <= 16) and 32, which gather
+# regulator states by ballots, and 64, with 8 regulator slots, 16 slots
+# (largest in-degree 9-16) or the ballot masks (largest in-degree above 16)
 SHAPES = [
     (5, 9, 1, 6, 3, (0, 0)),
     (16, 40, 3, 12, 8, (1, 1)),
@@ -54,13 +54,14 @@ SHAPES = [
 def _variant(prob):
     """(lanes per chain, regulator slots) the library picks for a network."""
     N, max_in = prob["n_nodes"], int(np.diff(prob["row_ptr"]).max())
-    return (16 if N <= 16 else 32 if N <= 32 else 64, 8 if max_in <= 8 else 16 if max_in <= 16 else 0)
+    lc = 16 if N <= 16 else 32 if N <= 32 else 64
+    return (lc, 0 if lc <= 32 else 8 if max_in <= 8 else 16 if max_in <= 16 else 0)
 
 
 def test_shapes_cover_every_kernel_variant():
     got = {_variant(priority_problem(300 + N, n_nodes=N, n_edges=E, n_cond=1, n_steps=2, n_obs=2)[0])
            for N, E, *_ in SHAPES}
-    assert got == {(16, 8), (16, 16), (32, 8), (32, 16), (32, 0), (64, 8), (64, 16), (64, 0)}
+    assert got == {(16, 0), (32, 0), (64, 8), (64, 16), (64, 0)}
 
 
 def _vectors(prob, n, seed):
