@@ -102,13 +102,13 @@ __global__ __launch_bounds__(kBlock) void pr_stage_kernel(DevProblem pb, StageAr
   PrAddr<DMAX> ad;
   pr_build<LC, DMAX>(pb, li, base, xv, nd, ad);
   int vcur = pr_violations<LC, DMAX>(pb, li, nd);
-  // Table 1: every stage starts by scoring the vector it restarts from
   // What this lane's node did in the current trajectory (kPrTold, ...),
   // recorded only where a wave holds one chain: with several chains per wave
   // a simulation is skipped only when all of them can skip it, which rarely
   // pays for the bookkeeping in every time step.
   constexpr bool kTrackActs = LC == 64;
   uint32_t acur = kPrTold | kPrReady | kPrFar | kPrVisited;
+  // Table 1: every stage starts by scoring the vector it restarts from
   int mcur = seg_sum<LC>(pr_mismatch<LC, DMAX, false>(pb, li, base, nd, ad, lstart, lobs, nullptr,
                                                       kTrackActs ? &acur : nullptr));
   int ccur = mcur + pb.lambda * vcur;
