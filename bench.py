@@ -389,8 +389,9 @@ def main() -> int:
     ap.add_argument("--trace-workload", default="c2", choices=["c1", "c2", "c3"])
     ap.add_argument("--epochs", type=int, default=4)
     ap.add_argument("--lr", type=float, default=1e-3)
-    ap.add_argument("--refresh", type=int, default=16)
-    ap.add_argument("--eps", type=float, default=0.1)
+    ap.add_argument("--refresh", type=int, default=64, help="learned: steps between proposal-table refreshes")
+    ap.add_argument("--eps", type=float, default=0.5,
+                    help="learned: fraction of candidates drawn by Table 1's plain rule")
     ap.add_argument("--eval-seeds", type=int, default=5)
     ap.add_argument("--model-seed", type=int, default=2005)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
