@@ -389,8 +389,8 @@ def main() -> int:
     ap.add_argument("--trace-workload", default="c2", choices=["c1", "c2", "c3"])
     ap.add_argument("--epochs", type=int, default=4)
     ap.add_argument("--lr", type=float, default=1e-3)
-    ap.add_argument("--refresh", type=int, default=64, help="learned: steps between proposal-table refreshes")
-    ap.add_argument("--eps", type=float, default=0.5,
+    ap.add_argument("--refresh", type=int, default=256, help="learned: steps between proposal-table refreshes")
+    ap.add_argument("--eps", type=float, default=0.9,
                     help="learned: fraction of candidates drawn by Table 1's plain rule")
     ap.add_argument("--eval-seeds", type=int, default=5)
     ap.add_argument("--model-seed", type=int, default=2005)
