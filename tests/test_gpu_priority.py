@@ -234,3 +234,29 @@ def test_full_size_stages_sampled_chains(name):
         assert cb1[chain] == ref["chain_best"][0], chain
         assert np.array_equal(cx1[chain], ref["chain_xbest"][0]), chain
     assert np.array_equal(o.cost_batch(cx1[:6]), cb1[:6].astype(np.int64))
+
+
+@pytest.mark.parametrize("N,E,C,T,n,L,hard", [
+    (2, 2, 1, 1, 1, 1, 1),          # the smallest network, one step, one chain, one annealing step
+    (64, 1300, 20, 3, 5, 70, 1),    # the largest segment, in-degree above 16 (ballot masks), many conditions
+    (40, 0, 3, 6, 7, 40, 0),        # no edges at all (penalty mode): only node parameters change
+    (16, 30, 2, 40, 9, 17, 1),      # a horizon longer than a step block; L not a multiple of the segment
+])
+def test_run_extreme_shapes(N, E, C, T, n, L, hard):
+    if E == 0:
+        row_ptr, src = np.zeros(N + 1, np.int32), np.zeros(0, np.int32)
+        rng = synth.rng_for(N)
+        init, clamp = synth.conditions(rng, N, C, (0, 1))
+        prob = dict(n_nodes=N, n_edges=0, row_ptr=row_ptr, src=src, n_cond=C, init=init, clamp=clamp, n_steps=T,
+                    obs_t=np.arange(T + 1, dtype=np.int32), obs_n=np.arange(0, N, 3, dtype=np.int32),
+                    step_size=1, hard=0, penalty=0, model=synth.MODEL_PRIORITY)
+        prob["observed"] = rng.integers(0, 3, size=(C, T + 1, len(prob["obs_n"]))).astype(np.int8)
+        x0 = synth.priority_random_params(rng, n, 0, N)
+    else:
+        prob, _ = priority_problem(900 + N, n_nodes=N, n_edges=E, n_cond=C, n_steps=T, n_obs=max(1, N // 3),
+                                   noise=0.1, clamps=(0, 2) if C > 1 else (0, 0), hard=hard)
+        x0 = synth.priority_feasible_params(synth.rng_for(N + 1), n, prob["row_ptr"], prob["src"])
+    _compare_runs(prob, x0, 21, T0=1.3, rho=0.75, n_stages=2, L=L)
+    xs = np.concatenate([x0, synth.priority_random_params(synth.rng_for(E + 3), 9, E, N)])
+    got = _sa().Problem(prob).eval_cost(_dev(xs)).cpu().numpy().astype(np.int64)
+    assert np.array_equal(got, OracleProblem(prob).cost_batch(xs))
