@@ -235,7 +235,10 @@ typedef struct {
  * (or desc->kernel = SA_KERNEL_PERSISTENT) run in one persistent launch per
  * stage and step size, networks up to 159 nodes; problem p draws its Philox
  * blocks with network id p.  Autotuning (chains_per_block = 0) runs the first
- * stage once per candidate before returning; results do not depend on it. */
+ * stage once per candidate before returning; results do not depend on it.
+ * A problem of SA_MODEL_PRIORITY runs alone (n_probs = 1), with
+ * SA_KERNEL_AUTO and plain proposals, on its own stage kernel (else
+ * SA_ERR_UNSUPPORTED); island restarts, resume and graphs apply as above. */
 int sa_run_create(sa_problem *const *probs, int32_t n_probs, const sa_run_desc *desc,
                   const int8_t *x0_dev, sa_run **out, void *stream);
 
