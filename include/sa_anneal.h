@@ -18,7 +18,10 @@
  *     node has an activating (+1) in-edge; cost = M + lambda * V where V counts
  *     the failing nodes of (a) plus those of (b);
  *   - search: Table 1 (parallel simulated annealing with a global restart from
- *     the best chain after every temperature stage).
+ *     the best chain after every temperature stage);
+ *   - the paper's own parameterisation with the priority update of §2.2 is
+ *     selected per problem (SA_MODEL_PRIORITY below); objective, constraints
+ *     and search are the same.
  *
  * Conventions of every entry point:
  *   - return 0 (SA_OK) on success, a negative SA_ERR_* code on failure; the
