@@ -239,8 +239,9 @@ typedef struct {
  * stage and step size, networks up to 159 nodes; problem p draws its Philox
  * blocks with network id p.  Autotuning (chains_per_block = 0) runs the first
  * stage once per candidate before returning; results do not depend on it.
- * A problem of SA_MODEL_PRIORITY runs alone (n_probs = 1), with
- * SA_KERNEL_AUTO and plain proposals, on its own stage kernel (else
+ * Problems of SA_MODEL_PRIORITY run on their own stage kernel, one launch
+ * per problem and stage (problem p with network id p), with SA_KERNEL_AUTO
+ * and plain proposals, and are not mixed with synchronous ones in a run (else
  * SA_ERR_UNSUPPORTED); island restarts, resume and graphs apply as above. */
 int sa_run_create(sa_problem *const *probs, int32_t n_probs, const sa_run_desc *desc,
                   const int8_t *x0_dev, sa_run **out, void *stream);

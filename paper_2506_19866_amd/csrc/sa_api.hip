@@ -646,29 +646,33 @@ static int enqueue_stage(sa_run *r, int32_t st, hipStream_t stream) {
   const bool timed = !r->ev_start.empty();
   if (timed) SA_HIP(hipEventRecord(r->ev_start[st], stream), "event record");
   if (!r->persistent) {
-    const sa::DevProblem &pb = r->probs[0]->dev;
-    sa::StageArgs a{};
-    a.n_chains = r->n;
-    a.seed = r->desc.seed;
-    a.net = 0;
-    a.stage = r->desc.first_stage + st;
-    a.L = r->desc.steps_per_stage;
-    a.dcap = r->dcap[st];
-    a.tau = r->tau + r->tau_off[st];
-    a.x_start = first ? r->x0 : r->xwin;
-    a.x_start_stride = first ? pb.P : 0;
-    a.group = first ? 0 : r->group;
-    a.xbest = r->xbest;
-    a.cbest = r->cbest;
-    a.cstats = r->cstats;
-    if (r->learned) {
-      sa::LearnedArgs la = r->la;
-      la.lt = r->lt[st];
-      SA_HIP((hipError_t)sa::launch_learned_stage(pb, a, la, stream), "learned stage launch");
-    } else if (pb.model == SA_MODEL_PRIORITY) {
-      SA_HIP((hipError_t)sa::launch_priority_stage(pb, a, stream), "priority stage launch");
-    } else {
-      SA_HIP((hipError_t)sa::launch_stage(pb, a, stream), "stage launch");
+    // one launch per problem (several only for the priority model); problem
+    // p draws its Philox blocks with network id p
+    for (int p = 0; p < np; ++p) {
+      const sa::DevProblem &pb = r->probs[p]->dev;
+      sa::StageArgs a{};
+      a.n_chains = r->n;
+      a.seed = r->desc.seed;
+      a.net = p;
+      a.stage = r->desc.first_stage + st;
+      a.L = r->desc.steps_per_stage;
+      a.dcap = r->dcap[st];
+      a.tau = r->tau + r->tau_off[st];
+      a.x_start = first ? r->x0 + r->x_off[p] : r->xwin + r->w_off[p];
+      a.x_start_stride = first ? pb.P : 0;
+      a.group = first ? 0 : r->group;
+      a.xbest = r->xbest + r->x_off[p];
+      a.cbest = r->cbest + (size_t)p * r->n;
+      a.cstats = r->cstats + (size_t)p * r->n * sa::kStatWords;
+      if (r->learned) {
+        sa::LearnedArgs la = r->la;
+        la.lt = r->lt[st];
+        SA_HIP((hipError_t)sa::launch_learned_stage(pb, a, la, stream), "learned stage launch");
+      } else if (pb.model == SA_MODEL_PRIORITY) {
+        SA_HIP((hipError_t)sa::launch_priority_stage(pb, a, stream), "priority stage launch");
+      } else {
+        SA_HIP((hipError_t)sa::launch_stage(pb, a, stream), "stage launch");
+      }
     }
   } else {
     for (size_t k = 0; k < r->item_class_d.size(); ++k) {
@@ -800,15 +804,16 @@ extern "C" int sa_run_create(sa_problem *const *probs, int32_t n_probs, const sa
   }
   const bool priority = probs[0]->dev.model == SA_MODEL_PRIORITY;
   for (int i = 0; i < n_probs; ++i)
-    if ((probs[i]->dev.model == SA_MODEL_PRIORITY) != priority || (priority && n_probs > 1))
-      return fail(SA_ERR_UNSUPPORTED, "the priority model runs one problem per run");
+    if ((probs[i]->dev.model == SA_MODEL_PRIORITY) != priority)
+      return fail(SA_ERR_UNSUPPORTED, "problems of both models in one run");
   if (priority && (desc->kernel != SA_KERNEL_AUTO || learned || traced))
     return fail(SA_ERR_UNSUPPORTED, "the priority model runs on its own stage kernel with plain proposals");
   const int device = probs[0]->device;
   for (int i = 1; i < n_probs; ++i)
     if (probs[i]->device != device) return fail(SA_ERR_ARG, "problems on different devices");
   SA_HIP(hipSetDevice(device), "hipSetDevice");
-  const bool persistent = n_probs > 1 || desc->kernel == SA_KERNEL_PERSISTENT;
+  // several priority-model problems take one stage-kernel launch each
+  const bool persistent = !priority && (n_probs > 1 || desc->kernel == SA_KERNEL_PERSISTENT);
   if (persistent)
     for (int i = 0; i < n_probs; ++i)
       if (probs[i]->dev.nm > sa::kPersistentTilesM)
@@ -865,10 +870,13 @@ extern "C" int sa_run_create(sa_problem *const *probs, int32_t n_probs, const sa
       la.trace_first = (g0 + desc->trace_every - 1) / desc->trace_every * desc->trace_every;
     }
   } else if (priority) {
-    const size_t smem = sa::priority_stage_smem_bytes(probs[0]->dev);
-    if (smem > 64 * 1024) {
-      free_run(r);
-      return fail(SA_ERR_UNSUPPORTED, "priority stage kernel needs %zu bytes of LDS (> 64 KiB)", smem);
+    for (int i = 0; i < n_probs; ++i) {
+      const size_t smem = sa::priority_stage_smem_bytes(probs[i]->dev);
+      if (smem > 64 * 1024) {
+        free_run(r);
+        return fail(SA_ERR_UNSUPPORTED, "problem %d: priority stage kernel needs %zu bytes of LDS (> 64 KiB)", i,
+                    smem);
+      }
     }
   } else if (!persistent) {
     const size_t smem = sa::stage_smem_bytes(probs[0]->dev, sa::stage_waves_per_block(probs[0]->dev));

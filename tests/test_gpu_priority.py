@@ -182,8 +182,9 @@ def test_rejections():
     with pytest.raises(sa.SAError) as e:
         sa.Run(P, _dev(x0), kernel=sa.SA_KERNEL_PERSISTENT, **kw)
     assert e.value.code == sa.SA_ERR_UNSUPPORTED
-    with pytest.raises(sa.SAError) as e:
-        sa.Run([P, P], [_dev(x0), _dev(x0)], **kw)
+    c1 = synth.load_workload("c1")
+    with pytest.raises(sa.SAError) as e:           # the two models in one run
+        sa.Run([P, sa.Problem(c1)], [_dev(x0), _dev(synth.start_vectors("c1", c1, 4))], **kw)
     assert e.value.code == sa.SA_ERR_UNSUPPORTED
     bad = x0.copy()
     bad[0, 3 * w["n_edges"]] = 7                     # a speed outside {1..6, 10..12}
@@ -260,3 +261,29 @@ def test_run_extreme_shapes(N, E, C, T, n, L, hard):
     xs = np.concatenate([x0, synth.priority_random_params(synth.rng_for(E + 3), 9, E, N)])
     got = _sa().Problem(prob).eval_cost(_dev(xs)).cpu().numpy().astype(np.int64)
     assert np.array_equal(got, OracleProblem(prob).cost_batch(xs))
+
+
+def test_several_networks_in_one_run():
+    """Three priority-model networks of different segment widths in one run:
+    one stage-kernel launch per network and stage, one reduction for all;
+    network p draws with Philox network id p, so each must equal the oracle's
+    run of that network alone with net = p (island restarts, a graph)."""
+    sa = _sa()
+    probs = [synth.load_workload("q1"), priority_problem(1201, n_nodes=27, n_edges=80, n_cond=3, n_steps=9,
+                                                         n_obs=9, noise=0.1, clamps=(1, 1))[0],
+             synth.load_workload("q3")]
+    n, S, L, G = 11, 3, 40, 4
+    x0 = [synth.priority_feasible_params(synth.rng_for(40 + i), n, p["row_ptr"], p["src"]) for i, p in enumerate(probs)]
+    run = sa.Run([sa.Problem(p) for p in probs], [_dev(x) for x in x0], seed=99, T0=1.5, rho=0.8, n_stages=S,
+                 steps_per_stage=L, group_size=G, use_graph=True)
+    for i, (prob, x) in enumerate(zip(probs, x0)):
+        ref = OracleProblem(prob).run(x, seed=99, T0=1.5, rho=0.8, n_stages=S, steps_per_stage=L, net=i,
+                                      n_threads=8, group_size=G)
+        st = run.stats(i)
+        xb, cost, winner = run.best(i)
+        cb, cx = run.chain_best(i)
+        assert np.array_equal(st["best_cost"], ref["stage_best"]) and np.array_equal(st["winner"], ref["stage_winner"])
+        for k in ("accepted", "uphill", "neutral", "infeasible"):
+            assert np.array_equal(st[k], ref["stage_" + k]), (i, k)
+        assert cost == ref["cost"] and winner == ref["winner"] and np.array_equal(xb, ref["x"]), i
+        assert np.array_equal(cb.astype(np.int64), ref["chain_best"]) and np.array_equal(cx, ref["chain_xbest"]), i
