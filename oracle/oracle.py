@@ -195,6 +195,9 @@ class OracleProblem:
         return out
 
     def brute_force(self, with_costs: bool = False):
+        """Every candidate of the ternary (synchronous) model's 3^P vectors."""
+        if self.model != 0:
+            raise ValueError("exhaustive search covers the ternary synchronous model only")
         total = 3 ** self.n_params
         argmin = np.zeros(self.n_params, dtype=np.int8)
         nmin = np.zeros(1, dtype=np.int64)

@@ -544,8 +544,9 @@ int ora_run(const ora_problem *p, const ora_run_args *args, const int8_t *x0,
 /* Returns the minimum cost; writes the first minimiser and the number of    */
 /* minimisers; costs[3^P] (optional) receives every cost.                    */
 /* ------------------------------------------------------------------------ */
-/* (ternary model only: model 0) */
+/* Ternary model only (model 0): returns -1 for any other model. */
 int64_t ora_brute_force(const ora_problem *p, int8_t *argmin_x, int64_t *n_minima, int64_t *costs) {
+  if (p->model != 0) return -1;
   const int64_t P = ora_n_params(p);
   int64_t total = 1;
   for (int64_t i = 0; i < P; ++i) total *= 3;
