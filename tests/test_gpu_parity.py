@@ -308,24 +308,34 @@ def test_infeasible_start_is_rejected():
 # full-size workload, benchmark launch configuration, sampled chains
 # ---------------------------------------------------------------------------
 def test_c3_full_size_stage_sampled_chains():
-    """One stage of the c3 workload at its full chain count; every chain is
-    independent within a stage, so sampled chains are recomputed by the
-    oracle one by one with their own Philox chain ids."""
+    """Two stages of the c3 workload in the launch configuration bench.py
+    times (16384 chains x 500 steps); every chain is independent within a
+    stage, so sampled chains are recomputed by the oracle one by one with
+    their own Philox chain ids: stage 0 from their start vectors, stage 1 from
+    the stage-0 winner every chain restarted from."""
     w = synth.load_workload("c3")
     s = synth.bench_schedule("c3")
-    n = s["n_chains"]
+    n, L = s["n_chains"], s["steps_per_stage"]
     x0 = synth.start_vectors("c3", w, n)
     sa = _sa()
     P = sa.Problem(w)
-    L = 60
-    run = sa.Run(P, _dev(x0), seed=s["seed"], T0=s["T0"], rho=s["rho"], n_stages=1, steps_per_stage=L)
+    kw = dict(seed=s["seed"], T0=s["T0"], rho=s["rho"], steps_per_stage=L)
+    run = sa.Run(P, _dev(x0), n_stages=2, launch=False, **kw)
+    run.launch(1)
     cb, cx = run.chain_best()
     st = run.stats()
     o = OracleProblem(w)
-    for chain in (0, 1, 4095, 8191, 12345, n - 1):
-        ref = o.run(x0[chain:chain + 1], seed=s["seed"], T0=s["T0"], rho=s["rho"], n_stages=1,
-                    steps_per_stage=L, first_chain=chain)
+    sample = (0, 1, 4095, 12345, n - 1)
+    for chain in sample:
+        ref = o.run(x0[chain:chain + 1], n_stages=1, first_chain=chain, **kw)
         assert cb[chain] == ref["chain_best"][0], chain
         assert np.array_equal(cx[chain], ref["chain_xbest"][0]), chain
     assert st["best_cost"][0] == cb.min() and st["winner"][0] == int(np.argmin(cb))
     assert np.array_equal(o.cost_batch(cx[:8]), cb[:8].astype(np.int64))
+    winner = cx[int(np.argmin(cb))]
+    run.launch(1)
+    cb1, cx1 = run.chain_best()
+    for chain in sample[:3]:
+        ref = o.run(winner[None, :], n_stages=1, first_stage=1, first_chain=chain, **kw)
+        assert cb1[chain] == ref["chain_best"][0], chain
+        assert np.array_equal(cx1[chain], ref["chain_xbest"][0]), chain
