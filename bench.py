@@ -12,6 +12,12 @@ Prints ONE JSON line on stdout (progress goes to stderr).  The roofline figure
 is for the stage kernel, timed with HIP events recorded by the library on the
 launch stream; the CPU baseline is the oracle timed on a bounded sample of the
 same workload on the host cores.
+
+Other workloads and modes: --workload c1/c2 (smaller synchronous networks),
+c4 (256 uneven networks in one persistent launch per stage), q1/q2/q3 (the
+paper's own priority-update model; q2 and q3 have the HPG and Mtb networks'
+parameter counts); --mode learned / learned-cost (the learned proposal against
+the plain one), --mode sweep (the chain counts of the paper's Table 2).
 """
 from __future__ import annotations
 
