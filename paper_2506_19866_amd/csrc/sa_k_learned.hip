@@ -7,8 +7,8 @@
 
 namespace sa {
 
-// LDS of a block: the observation tables, the network fragments (when a
-// network is loaded), the parameter descriptors, then one area per wave.
+// LDS of a block: the observation tables, the parameter descriptors, then
+// one area per wave.
 template <int NM, int NK, int D>
 __global__ __launch_bounds__(256) void learned_stage_kernel(DevProblem pb, StageArgs sa, LearnedArgs la) {
   extern __shared__ uint32_t smem[];
@@ -16,21 +16,15 @@ __global__ __launch_bounds__(256) void learned_stage_kernel(DevProblem pb, Stage
   uint32_t *lds_r = smem, *lds_w = smem + n_obs;
   uint32_t *cursor = smem + 2 * n_obs;
   const bool model = la.w1f != nullptr;
-  uint4 *s_w1f = nullptr, *s_w2f = nullptr;
-  if (model) {
-    s_w1f = reinterpret_cast<uint4 *>(cursor);
-    s_w2f = s_w1f + kW1FragU4;
-    cursor += 4 * (kW1FragU4 + kW2FragU4);
-  }
+  // The network fragments (16.5 KB) stay in global memory, read through the
+  // caches at refreshes only: kept out of LDS, a workgroup's LDS lets three
+  // workgroups share a CU instead of two.
   uint32_t *s_pinfo = cursor;
   cursor += round4(pb.P);
   for (int i = threadIdx.x; i < n_obs; i += blockDim.x) {
     lds_r[i] = pb.obs_r[i];
     lds_w[i] = pb.obs_w[i];
   }
-  if (model)
-    stage_mlp_fragments(s_w1f, s_w2f, static_cast<const uint4 *>(la.w1f), static_cast<const uint4 *>(la.w2f),
-                        threadIdx.x, blockDim.x);
   for (int i = threadIdx.x; i < pb.P; i += blockDim.x) s_pinfo[i] = pb.param_info[i];
   __syncthreads();
 
@@ -56,8 +50,8 @@ __global__ __launch_bounds__(256) void learned_stage_kernel(DevProblem pb, Stage
   hk.pb = &pb;
   hk.la = la;
   hk.pinfo = s_pinfo;
-  hk.w1f = s_w1f;
-  hk.w2f = s_w2f;
+  hk.w1f = static_cast<const uint4 *>(la.w1f);
+  hk.w2f = static_cast<const uint4 *>(la.w2f);
   hk.xref = lds + chain_lds_bytes(pb);
   hk.tbl = reinterpret_cast<uint32_t *>(hk.xref + round4(pb.P));
   hk.msh = reinterpret_cast<float *>(hk.tbl + learned_tbl_words(pb));
@@ -72,7 +66,8 @@ __global__ __launch_bounds__(256) void learned_stage_kernel(DevProblem pb, Stage
 }
 
 size_t learned_smem_bytes(const DevProblem &pb, bool model) {
-  return (size_t)2 * obs_dwords(pb) * 4 + (model ? (size_t)16 * (kW1FragU4 + kW2FragU4) : 0) +
+  (void)model;
+  return (size_t)2 * obs_dwords(pb) * 4 +
          (size_t)4 * round4(pb.P) + (size_t)kWavesPerBlock * learned_wave_bytes(pb);
 }
 

@@ -36,7 +36,7 @@ __host__ __device__ inline int learned_tbl_words(const DevProblem &pb) {
   return 2 * pb.P > 3 * 128 * pb.nk ? 2 * pb.P : 3 * 128 * pb.nk;
 }
 // Feature rows of 32 moves staged between their computation and the tiles.
-constexpr int kStageMoves = 32;
+constexpr int kStageMoves = 16;
 // LDS of one chain: the plain chain area, the vector at the last refresh
 // [P4], the table, three float node features [N4] each, and the staged
 // feature rows (32 x 64 bytes).
@@ -218,7 +218,7 @@ struct LearnedHooks {
   const DevProblem *pb;
   LearnedArgs la;
   const uint32_t *pinfo;     // LDS copy of the parameter descriptors
-  const uint4 *w1f, *w2f;    // LDS copies of the network fragments, or null
+  const uint4 *w1f, *w2f;    // the network fragments (global memory), or null
   uint8_t *xref;             // vector at the last refresh
   uint32_t *tbl;             // cumulative weights (or aggregates during a refresh)
   float *msh, *eh, *ah;
