@@ -191,8 +191,8 @@ __global__ __launch_bounds__(256) void mlp_update_kernel(MlpUpdateArgs a) {
     for (int w = 0; w < a.waves; ++w) gsum += a.partial[(size_t)w * kMlpParams + q];
     if (a.grad_out) a.grad_out[q] = gsum;
     if (a.adam) {
-      const float m = a.beta1 * a.m[q] + (1.f - a.beta1) * gsum;
-      const float v = a.beta2 * a.v[q] + (1.f - a.beta2) * gsum * gsum;
+      const float m = a.beta1 * a.m[q] + a.omb1 * gsum;
+      const float v = a.beta2 * a.v[q] + a.omb2 * (gsum * gsum);
       a.m[q] = m;
       a.v[q] = v;
       a.master[q] -= a.lr * (m / a.bc1) / (sqrtf(v / a.bc2) + a.eps);

@@ -95,7 +95,10 @@ struct MlpUpdateArgs {
   float *grad_out;     // gradients mode: sums written here (no update)
   float *loss_out;     // optional: mean loss of the batch
   int adam;            // 1: Adam step on the masters
-  float lr, beta1, beta2, eps, bc1, bc2;  // bc = 1 - beta^t
+  // beta, 1 - beta and the bias corrections 1 - beta^t, each the float32
+  // rounding of its exact decimal value (1 - beta is not taken in float32:
+  // 1 - 0.999f is 1.3e-5 off in relative terms)
+  float lr, beta1, beta2, omb1, omb2, eps, bc1, bc2;
   float *master, *m, *v;
   uint4 *w1f, *w2f;
 };

@@ -293,13 +293,17 @@ def test_learned_run_captured_in_a_graph():
 
 def test_trained_network_gain_over_plain_candidates():
     """What the trained network gains over Table 1's uniform candidate, at
-    equal chain states: the network is trained on traces of plain c2 runs
-    (its own kernels, deterministic), then a traced learned run on c2 (other
-    seed, later stages) mixes table-drawn candidates with plain ones (eps);
-    the table's candidates are accepted improving moves more often than the
-    plain candidates drawn at the same steps (measured: 0.614% against 0.540%,
-    +14%, the same gain bench.py's learned mode reports on c3).  Everything
-    here is deterministic, so the figures are those of this code."""
+    equal chain states.  The network is trained on traces of plain c2 runs
+    (run seed 2002); five held-out run seeds (2102..2106, never used for
+    training or for choosing any setting) then run traced learned c2 runs that
+    draw a fraction eps of their candidates uniformly (Table 1, source 0) and
+    the rest from the network's table (source 1), at the same steps of the same
+    chains.  Declared before measuring: the table's candidates are accepted
+    improving moves more often than the uniform ones -- the lower end of the
+    99% two-sided interval (normal approximation, pooled over the seeds) of the
+    difference of the two rates is above zero, and the table wins on at least 4
+    of the 5 seeds.  Fallback candidates (sources 2, 3: the chain already holds
+    the drawn move's value, or no move is available) are in neither group."""
     sa = _sa()
     from paper_2506_19866_amd import proposal
     w = synth.load_workload("c2")
@@ -314,17 +318,29 @@ def test_trained_network_gain_over_plain_candidates():
     assert losses[-1] < losses[0]
     S = 12
     cap = S * L // 2
-    trace = torch.zeros((n, cap * sa.TRACE_RECORD_BYTES), dtype=torch.uint8, device="cuda")
-    run = sa.Run(P, x0, seed=s["seed"] + 1, T0=s["T0"], rho=s["rho"], first_stage=30, n_stages=S, steps_per_stage=L,
-                 model=net, refresh_every=16, eps_plain=0.25, trace=trace, trace_every=2)
-    run.best()
-    _, delta, flags = proposal.trace_rows(trace)
-    improving = (((flags & 1) != 0) & (delta < 0)).cpu().numpy()
-    source = ((flags >> 2) & 3).cpu().numpy()
-    table, plain = source == sa.SA_SOURCE_LEARNED, source != sa.SA_SOURCE_LEARNED
-    r_table, r_plain = improving[table].mean(), improving[plain].mean()
-    print(f"accepted improving: table candidates {r_table:.5f} ({table.sum()}), plain {r_plain:.5f} ({plain.sum()})")
-    assert table.sum() > 10000 and plain.sum() > 10000
-    assert r_table > 1.05 * r_plain, (r_table, r_plain)
-    run.close()
+    counts = []          # per seed: (improving table, table, improving uniform, uniform)
+    for seed in range(s["seed"] + 100, s["seed"] + 105):
+        trace = torch.zeros((n, cap * sa.TRACE_RECORD_BYTES), dtype=torch.uint8, device="cuda")
+        run = sa.Run(P, x0, seed=seed, T0=s["T0"], rho=s["rho"], first_stage=30, n_stages=S, steps_per_stage=L,
+                     model=net, refresh_every=16, eps_plain=0.25, trace=trace, trace_every=2)
+        run.best()
+        _, delta, flags = proposal.trace_rows(trace)
+        improving = (((flags & 1) != 0) & (delta < 0)).cpu().numpy()
+        source = ((flags >> 2) & 3).cpu().numpy()
+        table, uniform = source == sa.SA_SOURCE_LEARNED, source == sa.SA_SOURCE_PLAIN
+        counts.append((int(improving[table].sum()), int(table.sum()), int(improving[uniform].sum()),
+                       int(uniform.sum())))
+        run.close()
     net.close()
+    c = np.array(counts, dtype=np.float64)
+    for k1, n1, k0, n0 in c:
+        print(f"seed: table {k1 / n1:.5f} of {int(n1)}, uniform {k0 / n0:.5f} of {int(n0)}")
+    k1, n1, k0, n0 = c.sum(axis=0)
+    p1, p0 = k1 / n1, k0 / n0
+    se = np.sqrt(p1 * (1 - p1) / n1 + p0 * (1 - p0) / n0)
+    lo, hi = p1 - p0 - 2.576 * se, p1 - p0 + 2.576 * se
+    print(f"pooled: table {p1:.5f}, uniform {p0:.5f}, ratio {p1 / p0:.3f}, 99% interval of the difference "
+          f"[{lo:.5f}, {hi:.5f}]")
+    assert n0 > 50000 and n1 > 150000
+    assert lo > 0, (p1, p0, lo, hi)
+    assert int(np.sum(c[:, 0] / c[:, 1] > c[:, 2] / c[:, 3])) >= 4, counts

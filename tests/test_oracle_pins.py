@@ -541,3 +541,50 @@ def test_mlp_reference_adam_reduces_loss_and_bf16_rounding():
     for _ in range(60):
         M.adam(p, M.grads(X, y, **p), state, lr=1e-2)
     assert M.loss(X, y, **p) < 0.5 * first
+
+
+def _golden_value(expr: str) -> float:
+    """Evaluates the golden file's exact expressions: fractions, sums and products of
+    them and sqrt() of a fraction."""
+    import re
+    from fractions import Fraction
+    if "sqrt" not in expr:
+        return float(eval(re.sub(r"(\d+)", r"Fraction(\1)", expr), {"Fraction": Fraction}))
+    return float(eval(expr.replace("sqrt", "math.sqrt"), {"math": __import__("math")}))
+
+
+def test_mlp_reference_adam_matches_hand_worked_steps():
+    """Adam as published (Kingma and Ba, Algorithm 1), worked by hand on a scalar
+    over three steps: moments, bias corrections and the eps placement
+    (tests/golden/adam_scalar_three_steps.json)."""
+    from fractions import Fraction
+    from oracle import mlp_reference as M
+    gold = golden("adam_scalar_three_steps.json")
+    for case in gold["cases"]:
+        hyper = {k: float(Fraction(case[k])) for k in ("lr", "beta1", "beta2", "eps")}
+        p, state = {"w": np.array([float(Fraction(case["w0"]))])}, {}
+        for g, step in zip(case["grads"], case["steps"]):
+            M.adam(p, {"w": np.array([float(Fraction(g))])}, state, **hyper)
+            assert state["t"] == step["t"]
+            if "m" in step:   # dyadic moments are exact in float64
+                assert state["m_w"][0] == float(Fraction(step["m"])), (case["name"], step)
+                assert state["v_w"][0] == float(Fraction(step["v"])), (case["name"], step)
+            if "w" in step:
+                want = _golden_value(step["w"])
+                assert abs(p["w"][0] - want) <= 1e-14 * abs(want), (case["name"], step["t"], p["w"][0], want)
+        assert abs(p["w"][0] - case["w_final_decimal"]) <= 1e-14 * abs(case["w_final_decimal"]), case["name"]
+        if "w_final" in case:
+            assert abs(p["w"][0] - _golden_value(case["w_final"])) <= 1e-14, case["name"]
+    # the golden tells the betas apart: swapping them moves the third step
+    case = gold["cases"][0]
+    p, state = {"w": np.array([3.0])}, {}
+    for g in (2.0, -2.0, 4.0):
+        M.adam(p, {"w": np.array([g])}, state, lr=0.5, beta1=15 / 16, beta2=0.5, eps=0.0)
+    assert abs(p["w"][0] - case["w_final_decimal"]) > 1e-3
+    # and per-parameter state: two parameters with different gradients keep separate moments
+    p, state = {"a": np.array([3.0]), "b": np.array([3.0])}, {}
+    for g in case["grads"]:
+        gv = float(Fraction(g))
+        M.adam(p, {"a": np.array([gv]), "b": np.array([-gv])}, state, lr=0.5, beta1=0.5, beta2=15 / 16, eps=0.0)
+    assert abs(p["a"][0] - case["w_final_decimal"]) <= 1e-14 * 3
+    assert abs(p["b"][0] - (6.0 - case["w_final_decimal"])) <= 1e-14 * 3
