@@ -53,7 +53,8 @@ enum {
   SA_ERR_DEVICE = -5,      /* a HIP call failed */
   SA_ERR_OOM = -6,         /* device allocation failed */
   SA_ERR_UNSUPPORTED = -7, /* size beyond what the kernels handle (see sa_create_problem) */
-  SA_ERR_OVERFLOW = -8     /* the largest possible cost does not fit in int32 */
+  SA_ERR_OVERFLOW = -8,    /* the largest possible cost does not fit in int32 */
+  SA_ERR_ABORTED = -9      /* sa_run_launch: the run's abort flag is set, nothing was queued */
 };
 
 enum { SA_HARD = 0, SA_PENALTY = 1 };
@@ -188,6 +189,22 @@ typedef struct {
                                 from its own best chain (lowest chain id on ties) instead of the global
                                 best; 0 or >= n_chains is Table 1's global restart.  Stage statistics and
                                 sa_best still report the global best.  Plain proposals only. */
+  volatile int32_t *abort_flag_host;
+                             /* nullable.  Stopping a queued run at a stage boundary of Table 1's stage
+                                loop (the point where §2.4.1's loop reduces, restarts and cools; a
+                                checkpoint there is the winner's vector and the stage index): pinned host
+                                memory (hipHostMalloc, or a pinned torch tensor) that stays valid and
+                                pinned until the run is destroyed; else SA_ERR_ARG at creation.  Before
+                                every queued stage, graph-captured ones included, one small kernel reads the
+                                flag once (system scope); if it is non-zero, that stage and every later
+                                stage of the run return at their kernels' entry without writing anything,
+                                so the run keeps the state of its last completed stage, and sa_run_launch
+                                queues nothing while the flag reads non-zero (SA_ERR_ABORTED).  The flag is
+                                the caller's to set, at any time, from any host thread; the library never
+                                writes it.  sa_run_stages_done gives the stages that completed; resuming is
+                                a new run with first_stage advanced by that count and every chain's
+                                starting vector the winner's (sa_best; with island restarts each chain's
+                                group winner, from sa_chain_best), bit-identical to the uninterrupted run. */
 } sa_run_desc;
 
 enum { SA_KERNEL_AUTO = 0, SA_KERNEL_PERSISTENT = 1 };
@@ -254,15 +271,21 @@ int sa_run_launch(sa_run *run, int32_t n_stages, void *stream);
 int sa_run_chains(sa_problem *const *probs, int32_t n_probs, const sa_run_desc *desc,
                   const int8_t *x0_dev, sa_run **out, void *stream);
 
-/* Global best after the last launched stage: vector (host, [P]), its cost and
- * the chain it came from.  Synchronises the run's stream.  Any output may be NULL. */
+/* Global best after the last completed stage: vector (host, [P]), its cost and
+ * the chain it came from.  Synchronises the run's stream.  Any output may be NULL.
+ * SA_ERR_ARG if no stage has completed (none launched, or aborted before the first). */
 int sa_best(sa_run *run, int32_t prob, int8_t *x_host, int32_t *cost, int32_t *winner_chain);
 
 /* Kernel choices of a run (no synchronisation). */
 int sa_run_get_info(sa_run *run, sa_run_info *info);
 
-/* Statistics of every launched stage (host, [stages launched]).  Synchronises. */
+/* Statistics of every launched stage (host, [stages launched]).  Synchronises.
+ * Stages skipped by an abort read as all zero with best_cost = winner = -1. */
 int sa_stats(sa_run *run, int32_t prob, sa_stage_stats *stats_host);
+
+/* Stages of the run that have completed: the stages launched unless the abort
+ * flag skipped the rest (abort_flag_host).  Synchronises the run's stream. */
+int sa_run_stages_done(sa_run *run, int32_t *done);
 
 /* Every chain's best cost (host, [n_chains]) and vector (host, [n_chains*P])
  * after the last launched stage, before the restart.  Synchronises.  Either
@@ -316,6 +339,27 @@ int sa_mlp_gradients(sa_mlp *model, const uint16_t *x_dev, const float *y_dev, i
  * loss_dev (device, nullable) receives the batch's mean loss before the step. */
 int sa_mlp_train_step(sa_mlp *model, const uint16_t *x_dev, const float *y_dev, int64_t n, float lr,
                       float *loss_dev, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Measured instruction peaks, the denominators of the benchmark's roofline
+ * figures (not part of the method).  The annealing kernels are bound by
+ * 32-bit integer VALU issue, a floating-point -> fp4 packing conversion and
+ * fp4 matrix products; the chip's published figures cover floating-point
+ * arithmetic only, so each rate is measured on the device: every lane of a
+ * full-occupancy grid (8 waves per SIMD) runs 8 independent dependency
+ * chains of one instruction.
+ *   SA_PEAK_VALU_XOR, _ADD, _BITOP3: v_xor_b32, v_add_u32, v_bitop3_b32, in
+ *     32-bit lane-ops per second (64 per wave instruction);
+ *   SA_PEAK_CVT_FP4: v_cvt_scalef32_pk_fp4_f32 (2 floats to 2 fp4 codes),
+ *     wave instructions x 64 per second;
+ *   SA_PEAK_MFMA_FP4: the unscaled fp4 x fp4 16x16x128 matrix product, in
+ *     flops per second (2 x 16 x 16 x 128 per instruction).
+ * rate (host) receives the rate; ms (host, nullable) the best of two timed
+ * launches after a warm-up one.  Allocates a small buffer, synchronises
+ * `stream`. */
+enum { SA_PEAK_VALU_XOR = 0, SA_PEAK_VALU_ADD = 1, SA_PEAK_VALU_BITOP3 = 2, SA_PEAK_CVT_FP4 = 3,
+       SA_PEAK_MFMA_FP4 = 4 };
+int sa_measure_peak(int32_t kind, double *rate, double *ms, void *stream);
 
 /* Message of the last failure on the calling thread ("" if none). */
 const char *sa_last_error(void);

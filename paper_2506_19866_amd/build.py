@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsa_anneal.so")
 SOURCES = ["sa_api.hip", "sa_k_batch.hip", "sa_k_stage.hip", "sa_k_persist.hip", "sa_k_mlp.hip",
-           "sa_k_learned.hip", "sa_k_priority.hip"]
+           "sa_k_learned.hip", "sa_k_priority.hip", "sa_k_probe.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

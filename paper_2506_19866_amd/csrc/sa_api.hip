@@ -89,6 +89,9 @@ struct sa_run {
   bool learned = false;                  // learned proposal or trace: the learned-stage kernel
   sa::LearnedArgs la{};                  // its stage-independent part
   std::vector<float> lt;                 // per stage: f32(ln(T_k) / 5)
+  uint32_t *ctl = nullptr;               // device {stop word, stages completed}
+  const volatile int32_t *abort_host = nullptr;  // the caller's pinned flag, and its device address
+  const volatile int32_t *abort_dev = nullptr;
 };
 
 struct sa_mlp {
@@ -580,6 +583,7 @@ static void free_run(sa_run *r) {
   hipFree(r->w_off_dev);
   hipFree(r->item_net);
   hipFree(r->item_chain0);
+  hipFree(r->ctl);
   delete r;
 }
 
@@ -639,11 +643,15 @@ static int upload_items(sa_run *r, int waves) {
   return SA_OK;
 }
 
-// Queues stage `st` (index within the run) on `stream`.
-static int enqueue_stage(sa_run *r, int32_t st, hipStream_t stream) {
+// Queues stage `st` (index within the run) on `stream`.  `control`: the
+// stage takes part in the run's abort handling and stage count (not so for
+// the autotuner's trial stages).
+static int enqueue_stage(sa_run *r, int32_t st, hipStream_t stream, bool control = true) {
   const int np = (int)r->probs.size();
   const bool first = st == 0;
   const bool timed = !r->ev_start.empty();
+  const uint32_t *stop = control && r->abort_dev ? r->ctl : nullptr;
+  if (stop) SA_HIP((hipError_t)sa::launch_abort_gate(r->abort_dev, r->ctl, stream), "abort gate launch");
   if (timed) SA_HIP(hipEventRecord(r->ev_start[st], stream), "event record");
   if (!r->persistent) {
     // one launch per problem (several only for the priority model); problem
@@ -664,6 +672,7 @@ static int enqueue_stage(sa_run *r, int32_t st, hipStream_t stream) {
       a.xbest = r->xbest + r->x_off[p];
       a.cbest = r->cbest + (size_t)p * r->n;
       a.cstats = r->cstats + (size_t)p * r->n * sa::kStatWords;
+      a.stop = stop;
       if (r->learned) {
         sa::LearnedArgs la = r->la;
         la.lt = r->lt[st];
@@ -698,6 +707,7 @@ static int enqueue_stage(sa_run *r, int32_t st, hipStream_t stream) {
       a.xbest = r->xbest;
       a.cbest = r->cbest;
       a.cstats = r->cstats;
+      a.stop = stop;
       const int grid = std::max(1, std::min(a.n_items, r->cus * r->blocks_per_cu[k]));
       SA_HIP((hipError_t)sa::launch_persistent(a, r->item_class_cls[k], r->item_class_d[k], grid, r->class_smem[k],
                                                stream),
@@ -718,6 +728,8 @@ static int enqueue_stage(sa_run *r, int32_t st, hipStream_t stream) {
   ra.xwin = r->xwin;
   ra.rec = r->rec + (size_t)st * np;
   ra.queue = r->persistent ? r->queue : nullptr;
+  ra.ctl = control ? r->ctl : nullptr;
+  ra.st = st;
   SA_HIP((hipError_t)sa::launch_batch_reduce(ra, stream), "reduce launch");
   return SA_OK;
 }
@@ -740,7 +752,7 @@ static int autotune_waves(sa_run *r, hipStream_t s) {
       rc = hip_fail(e, "autotune");
       break;
     }
-    if ((rc = enqueue_stage(r, 0, s)) != SA_OK) break;
+    if ((rc = enqueue_stage(r, 0, s, false)) != SA_OK) break;
     float ms = 0.f;
     e = hipEventRecord(e1, s);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -782,6 +794,14 @@ extern "C" int sa_run_create(sa_problem *const *probs, int32_t n_probs, const sa
     return fail(SA_ERR_ARG, "chains_per_block must be 0 (autotune), 1, 2, 4 or 8");
   if (desc->record_times && desc->use_graph) return fail(SA_ERR_ARG, "record_times and use_graph exclude each other");
   if (desc->group_size < 0) return fail(SA_ERR_ARG, "group_size must be >= 0");
+  void *abort_dev = nullptr;
+  if (desc->abort_flag_host) {
+    hipError_t ae = hipHostGetDevicePointer(&abort_dev, const_cast<int32_t *>(desc->abort_flag_host), 0);
+    if (ae != hipSuccess || !abort_dev) {
+      (void)hipGetLastError();  // clear the sticky error the lookup leaves
+      return fail(SA_ERR_ARG, "abort_flag_host is not pinned host memory (hipHostMalloc)");
+    }
+  }
   const bool learned = desc->proposal == SA_PROPOSAL_LEARNED, traced = desc->trace_dev != nullptr;
   if (desc->proposal != SA_PROPOSAL_PLAIN && !learned) return fail(SA_ERR_ARG, "unknown proposal %d", desc->proposal);
   if (learned && !desc->model) return fail(SA_ERR_ARG, "the learned proposal needs a model");
@@ -829,6 +849,8 @@ extern "C" int sa_run_create(sa_problem *const *probs, int32_t n_probs, const sa
   r->n = n;
   r->persistent = persistent;
   r->stream = s;
+  r->abort_host = desc->abort_flag_host;
+  r->abort_dev = static_cast<const volatile int32_t *>(abort_dev);
   r->group = desc->group_size > 0 && desc->group_size < n ? desc->group_size : 0;
   const int64_t n_groups = r->group ? (n + r->group - 1) / r->group : 1;
   int64_t xo = 0, wo = 0;
@@ -935,6 +957,8 @@ extern "C" int sa_run_create(sa_problem *const *probs, int32_t n_probs, const sa
   alloc((void **)&r->w_off_dev, (size_t)n_probs * 8);
   alloc((void **)&r->item_net, (size_t)(n * n_probs) * 4);
   alloc((void **)&r->item_chain0, (size_t)(n * n_probs) * 4);
+  alloc((void **)&r->ctl, 2 * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMemsetAsync(r->ctl, 0, 2 * sizeof(uint32_t), s);
   for (int st = 0; st < S && desc->record_times && e == hipSuccess; ++st) {
     hipEvent_t a = nullptr, b = nullptr;
     e = hipEventCreate(&a);
@@ -1008,6 +1032,7 @@ extern "C" int sa_run_launch(sa_run *r, int32_t n_stages, void *stream) {
   SA_HIP(hipSetDevice(r->device), "hipSetDevice");
   hipStream_t s = (hipStream_t)stream;
   if (n_stages == 0) return SA_OK;
+  if (r->abort_host && *r->abort_host != 0) return fail(SA_ERR_ABORTED, "the run's abort flag is set; nothing queued");
   if (r->desc.use_graph) {
     // The stages of this call become one graph (no memset nodes inside),
     // captured on the run's own stream (the caller's may be the null stream,
@@ -1061,13 +1086,32 @@ static int sync_run(sa_run *r, int32_t prob) {
   return SA_OK;
 }
 
+// Stages of the run that have completed (after synchronising its stream):
+// the stages launched, unless an abort skipped the rest.
+static int stages_done(sa_run *r, int32_t &done) {
+  uint32_t ctl[2] = {0, 0};
+  SA_HIP(hipMemcpy(ctl, r->ctl, sizeof(ctl), hipMemcpyDeviceToHost), "copy run control");
+  done = (int32_t)std::min<uint32_t>(ctl[1], (uint32_t)r->launched);
+  return SA_OK;
+}
+
+extern "C" int sa_run_stages_done(sa_run *r, int32_t *done) {
+  if (!done) return fail(SA_ERR_ARG, "done is NULL");
+  int rc = sync_run(r, 0);
+  if (rc != SA_OK) return rc;
+  return stages_done(r, *done);
+}
+
 extern "C" int sa_best(sa_run *r, int32_t prob, int8_t *x_host, int32_t *cost, int32_t *winner) {
   int rc = sync_run(r, prob);
   if (rc != SA_OK) return rc;
   if (r->launched == 0) return fail(SA_ERR_ARG, "no stage launched");
+  int32_t done = 0;
+  if ((rc = stages_done(r, done)) != SA_OK) return rc;
+  if (done == 0) return fail(SA_ERR_ARG, "no stage completed (aborted before the first)");
   const size_t np = r->probs.size();
   sa::StageRecord rec;
-  SA_HIP(hipMemcpy(&rec, r->rec + (size_t)(r->launched - 1) * np + prob, sizeof(rec), hipMemcpyDeviceToHost),
+  SA_HIP(hipMemcpy(&rec, r->rec + (size_t)(done - 1) * np + prob, sizeof(rec), hipMemcpyDeviceToHost),
          "copy record");
   // the global winner is also the winner of its restart group
   const int64_t P = r->probs[prob]->dev.P;
@@ -1084,11 +1128,19 @@ extern "C" int sa_stats(sa_run *r, int32_t prob, sa_stage_stats *out) {
   if (rc != SA_OK) return rc;
   if (!out) return fail(SA_ERR_ARG, "out is NULL");
   const size_t np = r->probs.size();
+  int32_t done = 0;
+  if ((rc = stages_done(r, done)) != SA_OK) return rc;
   std::vector<sa::StageRecord> rec((size_t)r->launched * np);
-  if (r->launched)
-    SA_HIP(hipMemcpy(rec.data(), r->rec, rec.size() * sizeof(sa::StageRecord), hipMemcpyDeviceToHost),
+  if (done)
+    SA_HIP(hipMemcpy(rec.data(), r->rec, (size_t)done * np * sizeof(sa::StageRecord), hipMemcpyDeviceToHost),
            "copy records");
   for (int32_t i = 0; i < r->launched; ++i) {
+    if (i >= done) {  // skipped by an abort
+      out[i] = sa_stage_stats{};
+      out[i].best_cost = -1;
+      out[i].winner = -1;
+      continue;
+    }
     const sa::StageRecord &x = rec[(size_t)i * np + prob];
     out[i].best_cost = x.best_cost;
     out[i].winner = x.winner;
@@ -1142,6 +1194,43 @@ extern "C" int sa_destroy_run(sa_run *r) {
   hipSetDevice(r->device);
   hipStreamSynchronize(r->stream);
   free_run(r);
+  return SA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// measured instruction peaks
+// ---------------------------------------------------------------------------
+extern "C" int sa_measure_peak(int32_t kind, double *rate, double *ms_out, void *stream) {
+  if (!rate) return fail(SA_ERR_ARG, "rate is NULL");
+  if (kind < SA_PEAK_VALU_XOR || kind > SA_PEAK_MFMA_FP4) return fail(SA_ERR_ARG, "unknown peak kind %d", kind);
+  hipStream_t s = (hipStream_t)stream;
+  int dev = 0, cus = 0;
+  SA_HIP(hipGetDevice(&dev), "hipGetDevice");
+  SA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "device attribute");
+  // 8 workgroups of 4 waves per CU: 8 waves per SIMD
+  const int blocks = std::max(cus, 1) * 8, threads = 256;
+  void *sink = nullptr;
+  SA_HIP(hipMalloc(&sink, (size_t)blocks * threads * 4), "hipMalloc(probe)");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  float best = 0.f;
+  for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {  // the first launch warms up clocks and code
+    e = hipEventRecord(e0, s);
+    if (e == hipSuccess) e = (hipError_t)sa::launch_probe(kind, sink, blocks, threads, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    if (e == hipSuccess && rep > 0 && (best == 0.f || t < best)) best = t;
+  }
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  hipFree(sink);
+  if (e != hipSuccess) return hip_fail(e, "peak probe");
+  if (!(best > 0.f)) return fail(SA_ERR_DEVICE, "peak probe: no time measured");
+  *rate = sa::probe_work(kind, blocks, threads) / (best * 1e-3);
+  if (ms_out) *ms_out = best;
   return SA_OK;
 }
 
@@ -1292,11 +1381,14 @@ extern "C" int sa_mlp_train_step(sa_mlp *m, const uint16_t *x, const float *y, i
   u.loss_out = loss;
   u.adam = 1;
   u.lr = lr;
-  u.beta1 = 0.9f;
-  u.beta2 = 0.999f;
+  const double beta1 = 0.9, beta2 = 0.999;
+  u.beta1 = (float)beta1;
+  u.beta2 = (float)beta2;
+  u.omb1 = (float)(1.0 - beta1);
+  u.omb2 = (float)(1.0 - beta2);
   u.eps = 1e-8f;
-  u.bc1 = (float)(1.0 - std::pow(0.9, (double)m->steps));
-  u.bc2 = (float)(1.0 - std::pow(0.999, (double)m->steps));
+  u.bc1 = (float)(1.0 - std::pow(beta1, (double)m->steps));
+  u.bc2 = (float)(1.0 - std::pow(beta2, (double)m->steps));
   u.master = m->master;
   u.m = m->m;
   u.v = m->v;

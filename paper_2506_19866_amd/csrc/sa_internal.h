@@ -90,6 +90,7 @@ struct StageArgs {
   int8_t *xbest;          // [n_chains*P] out
   int32_t *cbest;         // [n_chains] out
   uint32_t *cstats;       // [n_chains*kStatWords] out
+  const uint32_t *stop;   // nullable: the run's stop word; non-zero: return at entry, writing nothing
 };
 
 // Per-chain statistics of a stage: accepted, uphill, neutral, infeasible
@@ -126,6 +127,7 @@ struct BatchArgs {
   int8_t *xbest;              // at x_off
   int32_t *cbest;             // [n_probs * n_chains]
   uint32_t *cstats;           // [n_probs * n_chains * kStatWords]
+  const uint32_t *stop;       // nullable: the run's stop word; non-zero: return at entry, writing nothing
 };
 
 // Table 1's serial part for every network of a run (one block per network):
@@ -144,6 +146,9 @@ struct BatchReduceArgs {
   int8_t *xwin;
   StageRecord *rec;           // [n_probs] of this stage
   uint32_t *queue;            // [kPersistentQueues] work counters to reset, or null
+  uint32_t *ctl;              // nullable: run control {stop word, stages completed}; with a non-zero stop
+                              // word the stage's reduction writes nothing, else it sets ctl[1] = st + 1
+  int32_t st;                 // stage index within the run
 };
 
 // One traced annealing step (the C ABI's sa_trace_record).
@@ -177,6 +182,15 @@ int stage_waves_per_block(const DevProblem &pb);
 int launch_persistent(const BatchArgs &a, int cls, int d, int grid, size_t smem, void *stream);
 int persistent_class(int nm);
 int launch_batch_reduce(const BatchReduceArgs &ra, void *stream);
+// Stage boundary of a run with a host abort flag: reads the flag once
+// (system scope, so the host's latest store is seen) and, if it is non-zero,
+// sets the run's stop word ctl[0], which every later kernel of the run reads
+// at entry.
+// Instruction-throughput probes (sa_k_probe.hip): the launch, and the work
+// one launch does (lane-ops, or flops for the matrix product).
+int launch_probe(int kind, void *sink, int blocks, int threads, void *stream);
+double probe_work(int kind, int blocks, int threads);
+int launch_abort_gate(const volatile int32_t *flag, uint32_t *ctl, void *stream);
 size_t persistent_smem_bytes(const DevProblem &pb, int waves);
 // Workgroups of `waves` waves with `smem` bytes of LDS of class cls that fit on one CU.
 int persistent_blocks_per_cu(int cls, int waves, size_t smem);

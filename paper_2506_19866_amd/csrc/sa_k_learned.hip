@@ -12,6 +12,7 @@ namespace sa {
 template <int NM, int NK, int D>
 __global__ __launch_bounds__(256) void learned_stage_kernel(DevProblem pb, StageArgs sa, LearnedArgs la) {
   extern __shared__ uint32_t smem[];
+  if (sa.stop && *sa.stop) return;  // the run was aborted at a stage boundary
   const int n_obs = obs_dwords(pb);
   uint32_t *lds_r = smem, *lds_w = smem + n_obs;
   uint32_t *cursor = smem + 2 * n_obs;

@@ -12,6 +12,7 @@ template <int MX, int KX, int D>
 __global__ __launch_bounds__(512) void persistent_kernel(BatchArgs a) {
   extern __shared__ uint32_t smem[];
   __shared__ int s_item;
+  if (a.stop && *a.stop) return;  // the run was aborted at a stage boundary
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = threadIdx.x >> 6;
   for (;;) {
@@ -55,6 +56,7 @@ __global__ __launch_bounds__(512) void persistent_kernel(BatchArgs a) {
 __global__ __launch_bounds__(256) void batch_reduce_kernel(BatchReduceArgs ra) {
   __shared__ unsigned long long keys[256];
   __shared__ unsigned long long sums[kStatWords][256];
+  if (ra.ctl && ra.ctl[0]) return;  // the run was aborted at a stage boundary
   const int tid = threadIdx.x;
   const int net = blockIdx.x;
   const int64_t base = (int64_t)net * ra.n_chains;
@@ -92,6 +94,7 @@ __global__ __launch_bounds__(256) void batch_reduce_kernel(BatchReduceArgs ra) {
     r->simulated = sums[4][0];
     if (net == 0 && ra.queue)  // one work counter per (size class, step size) launch
       for (int q = 0; q < kPersistentQueues; ++q) ra.queue[q] = 0u;
+    if (net == 0 && ra.ctl) ra.ctl[1] = (uint32_t)(ra.st + 1);
   }
   if (ra.group) return;  // every restart group copies its own winner (group_restart_kernel)
   const int P = ra.probs[net].P;
@@ -105,6 +108,7 @@ __global__ __launch_bounds__(256) void batch_reduce_kernel(BatchReduceArgs ra) {
 // chain (lowest chain id on ties) is copied to the group's winner slot, from
 // which every chain of the group starts the next stage.
 __global__ __launch_bounds__(256) void group_restart_kernel(BatchReduceArgs ra, int64_t groups_per_net) {
+  if (ra.ctl && ra.ctl[0]) return;  // the run was aborted at a stage boundary
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t gid = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   if (gid >= (int64_t)ra.n_probs * groups_per_net) return;
@@ -127,6 +131,12 @@ __global__ __launch_bounds__(256) void group_restart_kernel(BatchReduceArgs ra, 
   const int8_t *from = ra.xbest + ra.x_off[net] + winner * P;
   int8_t *to = ra.xwin + ra.w_off[net] + g * P;
   for (int i = lane; i < P; i += kWave) to[i] = from[i];
+}
+
+__global__ void abort_gate_kernel(const volatile int32_t *flag, uint32_t *ctl) {
+  if (threadIdx.x != 0) return;
+  const int32_t f = __hip_atomic_load(const_cast<const int32_t *>(flag), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  if (f != 0) ctl[0] = 1u;
 }
 
 size_t persistent_smem_bytes(const DevProblem &pb, int waves) {
@@ -170,6 +180,11 @@ int launch_persistent(const BatchArgs &a, int cls, int d, int grid, size_t smem,
       return (int)hipErrorInvalidValue;
   }
 #undef SA_CASE
+  return (int)hipGetLastError();
+}
+
+int launch_abort_gate(const volatile int32_t *flag, uint32_t *ctl, void *stream) {
+  abort_gate_kernel<<<1, 64, 0, (hipStream_t)stream>>>(flag, ctl);
   return (int)hipGetLastError();
 }
 

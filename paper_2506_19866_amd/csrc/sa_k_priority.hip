@@ -72,6 +72,7 @@ __host__ __device__ inline int pr_table_bytes(const DevProblem &pb) {
 template <int LC, int DMAX>
 __global__ __launch_bounds__(kBlock) void pr_stage_kernel(DevProblem pb, StageArgs sa) {
   extern __shared__ uint32_t smem[];
+  if (sa.stop && *sa.stop) return;  // the run was aborted at a stage boundary
   const int tb = pr_table_bytes(pb);
   uint8_t *lstart = reinterpret_cast<uint8_t *>(smem);
   uint32_t *lobs = reinterpret_cast<uint32_t *>(lstart + round4(pb.C * LC));

@@ -1,0 +1,114 @@
+// sa_k_probe.hip -- instruction-throughput probes: the measured peaks that
+// the benchmark's roofline figures divide by (the published chip figures
+// cover floating-point arithmetic only, and the annealing kernels are bound
+// by 32-bit integer VALU issue and the packing conversion).
+//
+// Every probe runs the whole GPU at full occupancy: each lane keeps 8
+// independent dependency chains of one instruction (so issue, not latency,
+// limits it), the loop body is unrolled 32 deep, and an empty asm statement
+// after every instruction makes its result opaque so the compiler cannot fold
+// the chain.  A result is stored only when it equals a value the host never
+// passes, which keeps the work alive without memory traffic.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "sa_anneal.h"
+
+namespace sa {
+namespace {
+
+constexpr int kProbeChains = 8;
+constexpr int kProbeUnroll = 4;  // x 8 chains = 32 instructions per loop trip
+
+template <int KIND>
+__global__ __launch_bounds__(256) void probe_valu_kernel(uint32_t *sink, int iters, uint32_t k0, uint32_t k1,
+                                                         uint32_t never) {
+  uint32_t a[kProbeChains];
+#pragma unroll
+  for (int j = 0; j < kProbeChains; ++j) a[j] = threadIdx.x * (2u * j + 1u) + blockIdx.x;
+  const float f0 = (float)(threadIdx.x & 7), f1 = -(float)(threadIdx.x & 3);
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int r = 0; r < kProbeUnroll; ++r)
+#pragma unroll
+      for (int j = 0; j < kProbeChains; ++j) {
+        if constexpr (KIND == SA_PEAK_VALU_XOR) a[j] = a[j] ^ k0;
+        if constexpr (KIND == SA_PEAK_VALU_ADD) a[j] = a[j] + k0;
+        if constexpr (KIND == SA_PEAK_VALU_BITOP3) a[j] = __builtin_amdgcn_bitop3_b32(a[j], k0, k1, 0xD8);
+        if constexpr (KIND == SA_PEAK_CVT_FP4)
+          a[j] = __builtin_amdgcn_cvt_scalef32_pk_fp4_f32(a[j], f0, f1, 0.125f, 0);
+        asm volatile("" : "+v"(a[j]));
+      }
+  }
+  uint32_t x = 0;
+#pragma unroll
+  for (int j = 0; j < kProbeChains; ++j) x ^= a[j];
+  if (x == never) sink[blockIdx.x * blockDim.x + threadIdx.x] = x;
+}
+
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Dense fp4 (e2m1) x fp4 products of the unscaled 16x16x128 form, the
+// instruction the annealing kernels run: 8 independent accumulators per wave.
+__global__ __launch_bounds__(256) void probe_mfma_fp4_kernel(float *sink, int iters, float never) {
+  v8i a = {}, b = {};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    a[j] = (int)(0x22222222u + threadIdx.x + j);
+    b[j] = (int)(0x44444444u - threadIdx.x - j);
+  }
+  v4f acc[kProbeChains];
+#pragma unroll
+  for (int j = 0; j < kProbeChains; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int r = 0; r < kProbeUnroll; ++r)
+#pragma unroll
+      for (int j = 0; j < kProbeChains; ++j)
+        acc[j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, acc[j], 4, 4, 0, 0, 0, 0);
+  }
+  float x = 0.f;
+#pragma unroll
+  for (int j = 0; j < kProbeChains; ++j) x += acc[j][0] + acc[j][1] + acc[j][2] + acc[j][3];
+  if (x == never) sink[blockIdx.x * blockDim.x + threadIdx.x] = x;
+}
+
+}  // namespace
+
+int probe_iters(int kind) { return kind == SA_PEAK_MFMA_FP4 ? 1024 : kind == SA_PEAK_CVT_FP4 ? 2048 : 8192; }
+
+double probe_work(int kind, int blocks, int threads) {
+  const double instr = (double)blocks * (threads / 64) * probe_iters(kind) * kProbeUnroll * kProbeChains;
+  return instr * (kind == SA_PEAK_MFMA_FP4 ? 2.0 * 16 * 16 * 128 : 64.0);
+}
+
+int launch_probe(int kind, void *sink, int blocks, int threads, void *stream) {
+  hipStream_t s = (hipStream_t)stream;
+  const int iters = probe_iters(kind);
+  const uint32_t k0 = 0x9E3779B9u, k1 = 0x7F4A7C15u, never = 0xFFFFFFFFu;
+  uint32_t *u = static_cast<uint32_t *>(sink);
+  switch (kind) {
+    case SA_PEAK_VALU_XOR:
+      probe_valu_kernel<SA_PEAK_VALU_XOR><<<blocks, threads, 0, s>>>(u, iters, k0, k1, never);
+      break;
+    case SA_PEAK_VALU_ADD:
+      probe_valu_kernel<SA_PEAK_VALU_ADD><<<blocks, threads, 0, s>>>(u, iters, k0, k1, never);
+      break;
+    case SA_PEAK_VALU_BITOP3:
+      probe_valu_kernel<SA_PEAK_VALU_BITOP3><<<blocks, threads, 0, s>>>(u, iters, k0, k1, never);
+      break;
+    case SA_PEAK_CVT_FP4:
+      probe_valu_kernel<SA_PEAK_CVT_FP4><<<blocks, threads, 0, s>>>(u, iters, k0, k1, never);
+      break;
+    case SA_PEAK_MFMA_FP4:
+      probe_mfma_fp4_kernel<<<blocks, threads, 0, s>>>(static_cast<float *>(sink), iters, -1.0e30f);
+      break;
+    default:
+      return (int)hipErrorInvalidValue;
+  }
+  return (int)hipGetLastError();
+}
+
+}  // namespace sa

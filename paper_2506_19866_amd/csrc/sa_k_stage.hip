@@ -10,6 +10,7 @@ namespace sa {
 template <int NM, int NK, int D>
 __global__ __launch_bounds__(256) void stage_kernel(DevProblem pb, StageArgs sa) {
   extern __shared__ uint32_t smem[];
+  if (sa.stop && *sa.stop) return;  // the run was aborted at a stage boundary
   const int n_obs = obs_dwords(pb);
   uint32_t *lds_r = smem, *lds_w = smem + n_obs;
   for (int i = threadIdx.x; i < n_obs; i += blockDim.x) {

@@ -16,7 +16,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsa_anne
 
 SA_OK = 0
 SA_ERR_ARG, SA_ERR_DOMAIN, SA_ERR_TOPOLOGY, SA_ERR_INFEASIBLE = -1, -2, -3, -4
-SA_ERR_DEVICE, SA_ERR_OOM, SA_ERR_UNSUPPORTED, SA_ERR_OVERFLOW = -5, -6, -7, -8
+SA_ERR_DEVICE, SA_ERR_OOM, SA_ERR_UNSUPPORTED, SA_ERR_OVERFLOW, SA_ERR_ABORTED = -5, -6, -7, -8, -9
 SA_HARD, SA_PENALTY = 0, 1
 SA_MODEL_SYNCHRONOUS, SA_MODEL_PRIORITY = 0, 1
 SA_KERNEL_AUTO, SA_KERNEL_PERSISTENT = 0, 1
@@ -29,9 +29,10 @@ TRACE_DTYPE = np.dtype([("features", "<u2", (32,)), ("param", "<i4"), ("value", 
 
 EXPORTS = ("sa_create_problem", "sa_destroy_problem", "sa_problem_get_info", "sa_eval_cost",
            "sa_simulate", "sa_run_create", "sa_run_launch", "sa_run_chains", "sa_best", "sa_stats",
-           "sa_chain_best", "sa_stage_times", "sa_run_get_info", "sa_destroy_run", "sa_mlp_create",
+           "sa_chain_best", "sa_stage_times", "sa_run_get_info", "sa_run_stages_done", "sa_destroy_run", "sa_mlp_create",
            "sa_mlp_destroy", "sa_mlp_get_params", "sa_mlp_set_params", "sa_mlp_forward", "sa_mlp_gradients",
-           "sa_mlp_train_step", "sa_last_error")
+           "sa_mlp_train_step", "sa_measure_peak", "sa_last_error")
+SA_PEAK_VALU_XOR, SA_PEAK_VALU_ADD, SA_PEAK_VALU_BITOP3, SA_PEAK_CVT_FP4, SA_PEAK_MFMA_FP4 = 0, 1, 2, 3, 4
 MLP_INPUTS, MLP_HIDDEN = 32, 256
 MLP_N_PARAMS = MLP_INPUTS * MLP_HIDDEN + MLP_HIDDEN + 1
 
@@ -70,7 +71,7 @@ class _RunDesc(C.Structure):
         ("use_graph", C.c_int32),
         ("proposal", C.c_int32), ("refresh_every", C.c_int32), ("model", C.c_void_p), ("eps_plain", C.c_double),
         ("trace_dev", C.c_void_p), ("trace_capacity", C.c_int64), ("trace_every", C.c_int32),
-        ("group_size", C.c_int64),
+        ("group_size", C.c_int64), ("abort_flag_host", C.c_void_p),
     ]
 
 
@@ -111,6 +112,7 @@ def lib():
         L.sa_chain_best.argtypes = [vp, C.c_int32, vp, vp]
         L.sa_stage_times.argtypes = [vp, C.c_int32, vp]
         L.sa_run_get_info.argtypes = [vp, C.POINTER(_RunInfo)]
+        L.sa_run_stages_done.argtypes = [vp, C.POINTER(C.c_int32)]
         L.sa_destroy_run.argtypes = [vp]
         L.sa_mlp_create.argtypes = [vp, C.POINTER(vp)]
         L.sa_mlp_destroy.argtypes = [vp]
@@ -119,6 +121,7 @@ def lib():
         L.sa_mlp_forward.argtypes = [vp, vp, C.c_int64, vp, vp]
         L.sa_mlp_gradients.argtypes = [vp, vp, vp, C.c_int64, vp, vp, vp]
         L.sa_mlp_train_step.argtypes = [vp, vp, vp, C.c_int64, C.c_float, vp, vp]
+        L.sa_measure_peak.argtypes = [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double), vp]
         L.sa_last_error.restype = C.c_char_p
         for name in EXPORTS:
             if name != "sa_last_error":
@@ -234,13 +237,17 @@ class Run:
                  steps_per_stage: int, first_stage: int = 0, stream=None, launch: bool = True,
                  record_times: bool = False, kernel: int = SA_KERNEL_AUTO, chains_per_block: int = 0,
                  use_graph: bool = False, model: "Mlp | None" = None, refresh_every: int = 16,
-                 eps_plain: float = 0.1, trace=None, trace_every: int = 1, group_size: int = 0):
+                 eps_plain: float = 0.1, trace=None, trace_every: int = 1, group_size: int = 0,
+                 abort_flag=None):
         """problems: a Problem or a list of them; x0: int8 CUDA tensor [n_chains, P]
         for one problem, or a list (one [n_chains, P_p] tensor per problem).
         model: learned proposal with this network; trace: uint8 CUDA tensor
         [n_chains, capacity * 80] receiving sa_trace_record rows (decode with
         decode_trace).  group_size G > 0: island restart, each group of G
-        consecutive chains restarts from its own best (0: the global best)."""
+        consecutive chains restarts from its own best (0: the global best).
+        abort_flag: a pinned int32 CPU tensor (torch pin_memory); setting its
+        first element non-zero stops the run at the next stage boundary
+        (stages_done() then counts the stages that completed)."""
         import torch
         if isinstance(problems, Problem):
             problems, x0 = [problems], [x0]
@@ -261,11 +268,18 @@ class Run:
                 raise ValueError("trace must be uint8 [n_chains, capacity * 80]")
             trace_ptr, cap = trace.data_ptr(), trace.shape[1] // TRACE_RECORD_BYTES
         self._trace, self.model = trace, model
+        abort_ptr = None
+        if abort_flag is not None:
+            if (not isinstance(abort_flag, torch.Tensor) or abort_flag.is_cuda or abort_flag.dtype != torch.int32
+                    or not abort_flag.is_pinned() or abort_flag.numel() < 1):
+                raise TypeError("abort_flag must be a pinned int32 CPU tensor")
+            abort_ptr = abort_flag.data_ptr()
+        self._abort = abort_flag
         d = _RunDesc(n, int(seed) & (2**64 - 1), float(T0), float(rho), int(first_stage), int(n_stages),
                      int(steps_per_stage), 1 if record_times else 0, int(kernel), int(chains_per_block),
                      1 if use_graph else 0, SA_PROPOSAL_LEARNED if model is not None else SA_PROPOSAL_PLAIN,
                      int(refresh_every), model.handle if model is not None else None, float(eps_plain),
-                     trace_ptr, int(cap), int(trace_every), int(group_size))
+                     trace_ptr, int(cap), int(trace_every), int(group_size), abort_ptr)
         probs = (C.c_void_p * len(self.problems))(*[p.handle for p in self.problems])
         h = C.c_void_p()
         _check(lib().sa_run_create(probs, len(self.problems), C.byref(d), C.c_void_p(self._x0.data_ptr()),
@@ -277,6 +291,13 @@ class Run:
     def launch(self, n_stages: int, stream=None):
         _check(lib().sa_run_launch(self._h, int(n_stages), _stream_handle(stream)))
         self.launched += n_stages
+
+    def stages_done(self) -> int:
+        """Stages that completed (all launched ones unless the abort flag
+        stopped the run).  Synchronises."""
+        d = C.c_int32()
+        _check(lib().sa_run_stages_done(self._h, C.byref(d)))
+        return d.value
 
     def info(self) -> dict:
         i = _RunInfo()
@@ -416,3 +437,12 @@ def decode_trace(trace) -> np.ndarray:
 
 def bf16_bits_to_float(bits) -> np.ndarray:
     return (np.asarray(bits, dtype=np.uint32) << 16).view(np.float32)
+
+
+def measure_peak(kind: int, stream=None) -> tuple[float, float]:
+    """Measured device-wide rate of one instruction kind (SA_PEAK_*): 32-bit
+    lane-ops per second for the VALU kinds and the packing conversion, flops
+    per second for the fp4 matrix product; and the timed launch's ms."""
+    rate, ms = C.c_double(), C.c_double()
+    _check(lib().sa_measure_peak(int(kind), C.byref(rate), C.byref(ms), _stream_handle(stream)))
+    return rate.value, ms.value
