@@ -33,9 +33,16 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# chip constants (MI355X): 256 CUs x 4 SIMDs x 16 lanes of 32-bit integer ALU at 2.4 GHz
-CU, SIMD_PER_CU, LANES, CLOCK_HZ = 256, 4, 16, 2.4e9
-ALU_PEAK_OPS = CU * SIMD_PER_CU * LANES * CLOCK_HZ          # 39.3e12 int32 lane-ops/s
+# chip figures (MI355X): 256 CUs of 4 SIMDs at 2.4 GHz; a SIMD issues one
+# wave64 VALU instruction every 4 cycles (16 lanes per cycle), so the 32-bit
+# integer ALU peak is 256 x 64 lane-ops per clock = 39.3e12 lane-ops/s (the
+# published 157.3 TFLOP/s fp32 vector rate is this times 2 flops per FMA times
+# 2 for packed-fp32 instructions, which integer work does not have).  The dense
+# fp4 matrix peak is the published 10.1 PFLOP/s.  Both are checked against
+# the measured rates of sa_measure_peak (--mode peaks).
+CU, CLOCK_HZ = 256, 2.4e9
+ALU_PEAK_OPS = CU * 64 * CLOCK_HZ
+FP4_DENSE_PEAK_FLOPS = 10.1e15
 PROFILES = os.path.join(ROOT, "profiles")
 STAGE_KERNEL_SOURCES = ("paper_2506_19866_amd/csrc/sa_k_stage.hip", "paper_2506_19866_amd/csrc/sa_chain.h",
                         "paper_2506_19866_amd/csrc/sa_device.h", "paper_2506_19866_amd/csrc/sa_internal.h")
@@ -84,6 +91,77 @@ def algorithmic_alu_ops_priority(prob: dict) -> int:
     return 2 * C * T * E + 6 * C * T * N + 2 * C * K * O
 
 
+def regulator_macs(prob: dict) -> int:
+    """Regulator terms per full simulation (one multiply-add per condition,
+    step and edge), the part of the work the synchronous kernels run on the
+    fp4 matrix cores."""
+    return prob["n_cond"] * prob["n_steps"] * prob["n_edges"]
+
+
+def measured_peaks() -> dict:
+    """Device-wide rates of the instructions the kernels are bound by
+    (sa_measure_peak): 32-bit lane-ops/s of v_xor / v_add / v_bitop3, the
+    fp4 packing conversion's lane-ops/s, the fp4 matrix product's flops/s."""
+    from paper_2506_19866_amd import sa
+    kinds = {"valu_xor": sa.SA_PEAK_VALU_XOR, "valu_add": sa.SA_PEAK_VALU_ADD, "valu_bitop3": sa.SA_PEAK_VALU_BITOP3,
+             "cvt_fp4": sa.SA_PEAK_CVT_FP4, "mfma_fp4": sa.SA_PEAK_MFMA_FP4}
+    out = {k: sa.measure_peak(v)[0] for k, v in kinds.items()}
+    out["valu"] = max(out["valu_xor"], out["valu_add"], out["valu_bitop3"])
+    return out
+
+
+def counters_from_profiles(launch_key: str, kind: str = "stage"):
+    """Issued instructions per stage-kernel launch from the committed SQ
+    counter summary, or None when it is missing or the kernel sources changed
+    since it was taken."""
+    name = {"stage": "stage_kernel_c3_sq_pmc.json", "priority": "pr_stage_kernel_q3_sq_pmc.json"}[kind]
+    path = os.path.join(PROFILES, name)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_sources_sha256_16") != stage_kernel_hash(kind) or rec.get("launch") != launch_key:
+        return None
+    return rec
+
+
+def alu_roofline(ops_per_launch: float, avg_launch_s: float, peaks: dict | None, kernel: str, traffic,
+                 counters=None, macs_per_launch: float | None = None, dense_macs_per_launch: float | None = None
+                 ) -> dict:
+    """The roofline object: algorithmic integer ALU work against the derived
+    ALU peak (and the measured one), plus the matrix-core part of the work
+    against the dense fp4 peak and, from committed counters, the VALU
+    instructions the kernel actually issued."""
+    achieved = ops_per_launch / avg_launch_s
+    r = {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK_OPS / 1e12, "unit": "TOP/s",
+         "frac": achieved / ALU_PEAK_OPS, "traffic": traffic, "kernel": kernel,
+         "avg_launch_ms": avg_launch_s * 1e3, "ops_per_launch": ops_per_launch,
+         "peak_note": "derived from unit counts: 256 CUs x 64 lanes per clock x 2.4 GHz (32-bit integer lane-ops)"}
+    if peaks:
+        r["peak_measured"] = peaks["valu"] / 1e12
+        r["frac_measured"] = achieved / peaks["valu"]
+    if macs_per_launch is not None:
+        m = {"achieved": 2 * macs_per_launch / avg_launch_s / 1e12, "peak": FP4_DENSE_PEAK_FLOPS / 1e12,
+             "unit": "TFLOP/s", "what": "2 x regulator multiply-adds of the simulations run (algorithmic)"}
+        m["frac"] = m["achieved"] / m["peak"]
+        if dense_macs_per_launch is not None:
+            m["executed"] = 2 * dense_macs_per_launch / avg_launch_s / 1e12
+            m["executed_frac"] = m["executed"] / m["peak"]
+        if peaks:
+            m["peak_measured"] = peaks["mfma_fp4"] / 1e12
+        r["mfma"] = m
+    if counters:
+        issued = counters["sq_insts_valu_per_launch"] * 64 / (counters["avg_launch_ms"] * 1e-3)
+        r["valu_issued"] = {"lane_ops_per_s": issued / 1e12, "unit": "TOP/s",
+                            "frac": issued / ALU_PEAK_OPS,
+                            "frac_measured": issued / peaks["valu"] if peaks else None,
+                            "source": counters.get("file", "profiles"),
+                            "note": "SQ_INSTS_VALU x 64 lanes per launch / its duration: every issued VALU "
+                                    "instruction (incl. the packing conversions and the matrix instructions' "
+                                    "VALU-side count), not only the algorithmic ops"}
+    return r
+
+
 def traffic_from_profiles(launch_key: str, kind: str = "stage"):
     """HBM bytes per stage-kernel launch from the committed PMC summary, or
     None when it is missing or the kernel sources changed since."""
@@ -95,6 +173,11 @@ def traffic_from_profiles(launch_key: str, kind: str = "stage"):
     if rec.get("kernel_sources_sha256_16") != stage_kernel_hash(kind) or rec.get("launch") != launch_key:
         return None
     return rec.get("hbm_bytes_per_launch")
+
+
+# one-core oracle samples per workload: (chains, steps), a second or less each
+SERIAL_SAMPLE = {"c1": (64, 100), "c2": (16, 500), "c3": (4, 500), "q1": (64, 100), "q2": (16, 500),
+                 "q3": (4, 500)}
 
 
 def cpu_baseline(name: str, prob: dict, sched: dict, target_s: float) -> dict:
@@ -119,9 +202,20 @@ def cpu_baseline(name: str, prob: dict, sched: dict, target_s: float) -> dict:
         rate = chains * L / dt
         if dt >= 0.5 * target_s:
             break
-    return {"value": chains * L / dt, "unit": "chain-steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"{name} stage 0 of its schedule: {chains} chains x {L} steps "
-                      f"({chains * L} chain-steps, {dt:.1f} s, {threads} threads, serial C oracle per chain)"}
+    out = {"value": chains * L / dt, "unit": "chain-steps/s", "cores": threads, "kind": "oracle",
+           "sample": f"{name} stage 0 of its schedule: {chains} chains x {L} steps "
+                     f"({chains * L} chain-steps, {dt:.1f} s, {threads} threads, serial C oracle per chain)"}
+    # one core: a few chains of the same stage on one thread
+    serial_chains = SERIAL_SAMPLE.get(name, (4, L))
+    x = synth.start_vectors(name, prob, serial_chains[0])
+    t0 = time.perf_counter()
+    o.run(x, seed=sched["seed"], T0=sched["T0"], rho=sched["rho"], n_stages=1, steps_per_stage=serial_chains[1],
+          n_threads=1)
+    dt1 = time.perf_counter() - t0
+    out["serial_1core"] = {"value": serial_chains[0] * serial_chains[1] / dt1, "unit": "chain-steps/s", "cores": 1,
+                           "sample": f"{name}: {serial_chains[0]} chains x {serial_chains[1]} steps of stage 0, "
+                                     f"one thread ({dt1:.2f} s)"}
+    return out
 
 
 def bench_batch(args) -> int:
@@ -157,7 +251,9 @@ def bench_batch(args) -> int:
         sims_i = float(np.mean(st["simulated"].astype(np.float64)))
         ops += sims_i * algorithmic_alu_ops(prob)
     avg_stage_s = elapsed / args.steps
-    achieved = ops / avg_stage_s
+    peaks = measured_peaks()
+    roofline = alu_roofline(ops, avg_stage_s, peaks, "persistent_kernel<MX,KX,D>", None)
+    roofline["note"] = "stage time incl. the reduction (graph launch)"
     log(f"[bench] c4: {args.steps} stages in {elapsed:.3f} s: {value:.4g} chain-steps/s")
     out = {
         "metric": "SA chain-steps/s, batched uneven networks", "value": value, "unit": "chain-steps/s",
@@ -167,9 +263,7 @@ def bench_batch(args) -> int:
         "config": {"workload": f"c4: {len(probs)} networks of 10-150 nodes, {n} chains each x {L} steps per stage, "
                                f"one persistent launch per stage, stages in one hipGraph",
                    "chains_per_block": run.info()["chains_per_block"]},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK_OPS / 1e12, "unit": "TOP/s",
-                     "frac": achieved / ALU_PEAK_OPS, "traffic": None, "kernel": "persistent_kernel<1>",
-                     "avg_launch_ms": avg_stage_s * 1e3, "note": "stage time incl. the reduction (graph launch)"},
+        "roofline": roofline,
     }
     print(json.dumps(out), flush=True)
     run.close()
@@ -386,7 +480,8 @@ def main() -> int:
                          "q1-q3 = the paper's priority-update model (q2 HPG-sized, q3 Mtb-sized)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--mode", default="throughput", choices=["throughput", "learned", "learned-cost", "sweep"],
+    ap.add_argument("--mode", default="throughput",
+                    choices=["throughput", "learned", "learned-cost", "sweep", "peaks"],
                     help="learned: train the proposal network on c2 traces and compare time-to-target on c3; "
                          "learned-cost: per-stage cost of the learned kernel against the plain one on c3; "
                          "sweep: chain counts of the paper's Table 2 with global and island restarts on c3")
@@ -425,6 +520,12 @@ def main() -> int:
         print(json.dumps({"copy_bytes": nbytes, "copies": 5}), flush=True)
         return 0
     from paper_2506_19866_amd import sa, synth
+    if args.mode == "peaks":
+        peaks = measured_peaks()
+        print(json.dumps({"mode": "peaks", "unit": "lane-ops/s (VALU, conversion), flop/s (mfma_fp4)",
+                          "derived_alu_peak": ALU_PEAK_OPS, "published_fp4_dense_peak": FP4_DENSE_PEAK_FLOPS,
+                          **peaks}), flush=True)
+        return 0
     if args.mode == "learned":
         return bench_learned(args)
     if args.mode == "learned-cost":
@@ -475,7 +576,6 @@ def main() -> int:
     sims = stats["simulated"].astype(np.float64)
     ops_per_launch = float(np.mean(sims)) * per_sim
     avg_launch_s = float(np.mean(stage_ms)) * 1e-3
-    achieved = ops_per_launch / avg_launch_s
     launch_key = f"{name}:{n}x{L}"
     if priority:
         lc = 16 if prob["n_nodes"] <= 16 else 32 if prob["n_nodes"] <= 32 else 64
@@ -489,12 +589,20 @@ def main() -> int:
         traffic = traffic_from_profiles(launch_key)
         model = (f"Mtb-scale, {prob['n_nodes']} nodes, {prob['n_edges']} edges, {P.n_params} ternary params "
                  f"(synchronous update)")
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK_OPS / 1e12, "unit": "TOP/s",
-                "frac": achieved / ALU_PEAK_OPS, "traffic": traffic, "kernel": kernel,
-                "avg_launch_ms": float(np.mean(stage_ms)),
-                "ops_per_launch": ops_per_launch,
-                "simulations_per_launch": float(np.mean(sims)),
-                "candidates_per_launch": float(n * L)}
+    peaks = measured_peaks()
+    log(f"[bench] measured peaks: VALU {peaks['valu'] / 1e12:.1f} T lane-ops/s, fp4 conversion "
+        f"{peaks['cvt_fp4'] / 1e12:.1f} T, fp4 matrix {peaks['mfma_fp4'] / 1e12:.0f} TFLOP/s")
+    counters = counters_from_profiles(launch_key, "priority" if priority else "stage")
+    macs = dense = None
+    if not priority:
+        sims_mean = float(np.mean(sims))
+        macs = sims_mean * regulator_macs(prob)
+        t_last = int(np.max(prob["obs_t"]))
+        cols = -(-prob["n_cond"] // 16) * 16
+        dense = sims_mean * cols * t_last * 16 * info["tiles_m"] * 128 * info["frags_k"]
+    roofline = alu_roofline(ops_per_launch, avg_launch_s, peaks, kernel, traffic, counters, macs, dense)
+    roofline["simulations_per_launch"] = float(np.mean(sims))
+    roofline["candidates_per_launch"] = float(n * L)
     out = {
         "metric": "SA chain-steps/s at 723-param scale" if P.n_params == 723 else "SA chain-steps/s",
         "value": value, "unit": "chain-steps/s",
