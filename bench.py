@@ -100,11 +100,13 @@ def regulator_macs(prob: dict) -> int:
 
 def measured_peaks() -> dict:
     """Device-wide rates of the instructions the kernels are bound by
-    (sa_measure_peak): 32-bit lane-ops/s of v_xor / v_add / v_bitop3, the
-    fp4 packing conversion's lane-ops/s, the fp4 matrix product's flops/s."""
+    (sa_measure_peak): 32-bit lane-ops/s of v_xor / v_add / v_bitop3, values
+    per second of the fp4 (2 per instruction) and fp6 (32 per instruction)
+    packing conversions, flops/s of the fp4 x fp4 and fp4 x fp6 products."""
     from paper_2506_19866_amd import sa
     kinds = {"valu_xor": sa.SA_PEAK_VALU_XOR, "valu_add": sa.SA_PEAK_VALU_ADD, "valu_bitop3": sa.SA_PEAK_VALU_BITOP3,
-             "cvt_fp4": sa.SA_PEAK_CVT_FP4, "mfma_fp4": sa.SA_PEAK_MFMA_FP4}
+             "cvt_fp4": sa.SA_PEAK_CVT_FP4, "mfma_fp4": sa.SA_PEAK_MFMA_FP4, "cvt_fp6": sa.SA_PEAK_CVT_FP6,
+             "mfma_fp4_fp6": sa.SA_PEAK_MFMA_FP4_FP6}
     out = {k: sa.measure_peak(v)[0] for k, v in kinds.items()}
     out["valu"] = max(out["valu_xor"], out["valu_add"], out["valu_bitop3"])
     return out
@@ -310,10 +312,14 @@ def bench_learned(args) -> int:
     """The learned proposal against the plain one on the Mtb-scale workload:
     traces of plain runs on the HPG-scale workload (about args.trace_rows
     rows), the network trained on them, then plain and learned runs of the
-    full c3 schedule for several seeds, compared by the stage-kernel time
-    they need to reach (a) a cost that 80% of the plain runs reach (their
-    80th-percentile final cost, so the plain median time is defined) and (b)
-    the cost of the generating parameters on the noisy data."""
+    full c3 schedule for args.eval_seeds run seeds, compared by the
+    stage-kernel time they need to reach (a) a target cost fixed before the
+    evaluation (args.target; the default 1277 is the cost 80% of the plain
+    runs reached on the seeds the refresh interval and plain fraction were
+    chosen on, k = 0..9) and (b) the cost of the generating parameters on the
+    noisy data.  The default seeds, k = 10..19 (run seed = 2003 + 100 k), are
+    held out from that choice.  Trace collection and training are timed on
+    their own and are not in the time to target."""
     import torch
     from paper_2506_19866_amd import proposal, sa, synth
     p2, s2 = synth.load_workload(args.trace_workload), synth.bench_schedule(args.trace_workload)
@@ -347,7 +353,7 @@ def bench_learned(args) -> int:
     x3 = torch.from_numpy(synth.start_vectors("c3", p3, n3)).cuda()
     hidden_cost = int(P3.eval_cost(torch.from_numpy(p3["hidden"][None, :]).cuda()).item())
     curves = {"plain": [], "learned": []}
-    for k in range(args.eval_seeds):
+    for k in range(args.seed_offset, args.seed_offset + args.eval_seeds):
         seed = s3["seed"] + 100 * k
         for kind in ("plain", "learned"):
             extra = dict(model=net, refresh_every=args.refresh, eps_plain=args.eps) if kind == "learned" else {}
@@ -359,7 +365,7 @@ def bench_learned(args) -> int:
                 f"in {curves[kind][-1][0][-1]:.2f} s of stage kernels, "
                 f"{curves[kind][-1][2]:.5f} of steps accepted improving moves")
     finals = {k: [int(c[1][-1]) for c in v] for k, v in curves.items()}
-    target = int(np.percentile(finals["plain"], 80, method="lower"))
+    target = args.target
     tt = {k: [_time_to(c, target) for c in v] for k, v in curves.items()}
     th = {k: [_time_to(c, hidden_cost) for c in v] for k, v in curves.items()}
     total = {k: [float(c[0][-1]) for c in v] for k, v in curves.items()}
@@ -369,9 +375,32 @@ def bench_learned(args) -> int:
         slow (None when that median is infinite)."""
         m = float(np.median([np.inf if v is None else v for v in vals]))
         return m if np.isfinite(m) else None
+
+    def boot_median_ci(vals, reps=4000, seed=0):
+        """95% bootstrap interval of the median (unreached = infinitely slow;
+        an infinite end is reported as None)."""
+        x = np.array([np.inf if v is None else v for v in vals], dtype=np.float64)
+        rng = np.random.default_rng(seed)
+        meds = np.median(x[rng.integers(0, len(x), size=(reps, len(x)))], axis=1)
+        lo = np.percentile(meds, 2.5, method="lower")
+        hi = np.percentile(meds, 97.5, method="higher")
+        return [float(lo) if np.isfinite(lo) else None, float(hi) if np.isfinite(hi) else None]
+
+    # paired by seed: the learned run reaches the target first (ties and
+    # double misses are neither), with a two-sided sign test
+    wins = losses_ = 0
+    for a, b in zip(tt["learned"], tt["plain"]):
+        la, pb = np.inf if a is None else a, np.inf if b is None else b
+        wins += la < pb
+        losses_ += pb < la
+    from math import comb
+    n_sign = wins + losses_
+    p_sign = min(1.0, 2 * sum(comb(n_sign, i) for i in range(0, min(wins, losses_) + 1)) / 2 ** n_sign) \
+        if n_sign else 1.0
     value = med(tt["learned"])
     out = {
-        "metric": "c3 time to a cost 80% of plain runs reach, learned proposal", "value": value, "unit": "s",
+        "metric": "c3 stage-kernel time to the target cost (fixed before the evaluation), learned proposal",
+        "value": value, "unit": "s",
         "n_gpus": 1, "steps": S3, "warmup": 0, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "fp4 simulation, bf16 network",
         "data": f"synthetic (traces from {args.trace_workload} plain runs; evaluation on the stored c3 workload)",
@@ -381,11 +410,17 @@ def bench_learned(args) -> int:
                    "eval_seeds": args.eval_seeds, "epochs": args.epochs},
         "plain_time_to_target_s": tt["plain"], "learned_time_to_target_s": tt["learned"],
         "plain_median_s": med(tt["plain"]), "target_cost": target,
+        "seeds": [s3["seed"] + 100 * k for k in range(args.seed_offset, args.seed_offset + args.eval_seeds)],
+        "median_ci95_s": {k: boot_median_ci(v) for k, v in tt.items()},
+        "paired_learned_first": wins, "paired_plain_first": losses_, "sign_test_p": p_sign,
+        "final_best_median_ci95": {k: boot_median_ci(v) for k, v in finals.items()},
         "learned_over_plain": (value / med(tt["plain"])) if value is not None and med(tt["plain"]) else None,
+        "learned_median_incl_trace_and_training_s": (value + t_collect + t_train) if value is not None else None,
         "reached": {k: sum(v is not None for v in vals) for k, vals in tt.items()},
         "final_best_median": {k: float(np.median(v)) for k, v in finals.items()},
         "hidden_params_cost": hidden_cost, "plain_time_to_hidden_s": th["plain"],
-        "learned_time_to_hidden_s": th["learned"], "final_best": finals,
+        "learned_time_to_hidden_s": th["learned"],
+        "reached_hidden": {k: sum(v is not None for v in vals) for k, vals in th.items()}, "final_best": finals,
         "schedule_stage_kernel_s": total, "trace_collect_s": t_collect, "train_s": t_train,
         "train_epoch_losses": losses, "improving_fraction": pos, "held_out_auc": auc,
         "improving_steps_fraction": {k: [c[2] for c in v] for k, v in curves.items()},
@@ -497,7 +532,11 @@ def main() -> int:
     ap.add_argument("--refresh", type=int, default=256, help="learned: steps between proposal-table refreshes")
     ap.add_argument("--eps", type=float, default=0.9,
                     help="learned: fraction of candidates drawn by Table 1's plain rule")
-    ap.add_argument("--eval-seeds", type=int, default=5)
+    ap.add_argument("--eval-seeds", type=int, default=10)
+    ap.add_argument("--seed-offset", type=int, default=10,
+                    help="learned: first evaluation seed index k (run seed 2003 + 100 k); 0-9 chose R and eps")
+    ap.add_argument("--target", type=int, default=1277,
+                    help="learned: target cost, fixed before the evaluation")
     ap.add_argument("--model-seed", type=int, default=2005)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB device buffer five times: the reference kernel of known "
@@ -522,7 +561,7 @@ def main() -> int:
     from paper_2506_19866_amd import sa, synth
     if args.mode == "peaks":
         peaks = measured_peaks()
-        print(json.dumps({"mode": "peaks", "unit": "lane-ops/s (VALU, conversion), flop/s (mfma_fp4)",
+        print(json.dumps({"mode": "peaks", "unit": "lane-ops/s (valu_*), values/s (cvt_*), flop/s (mfma_*)",
                           "derived_alu_peak": ALU_PEAK_OPS, "published_fp4_dense_peak": FP4_DENSE_PEAK_FLOPS,
                           **peaks}), flush=True)
         return 0
@@ -591,7 +630,7 @@ def main() -> int:
                  f"(synchronous update)")
     peaks = measured_peaks()
     log(f"[bench] measured peaks: VALU {peaks['valu'] / 1e12:.1f} T lane-ops/s, fp4 conversion "
-        f"{peaks['cvt_fp4'] / 1e12:.1f} T, fp4 matrix {peaks['mfma_fp4'] / 1e12:.0f} TFLOP/s")
+        f"{peaks['cvt_fp4'] / 1e12:.1f} T values/s, fp4 matrix {peaks['mfma_fp4'] / 1e12:.0f} TFLOP/s")
     counters = counters_from_profiles(launch_key, "priority" if priority else "stage")
     macs = dense = None
     if not priority:

@@ -298,6 +298,7 @@ int sa_stage_times(sa_run *run, int32_t prob, float *ms_host);
 
 int sa_destroy_run(sa_run *run);
 
+
 /* ---------------------------------------------------------------------------
  * Learned proposal network.  An extension of Table 1's GetCandidate (not in
  * the paper): a network scores every single-parameter move of a chain from 32
@@ -350,15 +351,19 @@ int sa_mlp_train_step(sa_mlp *model, const uint16_t *x_dev, const float *y_dev, 
  * chains of one instruction.
  *   SA_PEAK_VALU_XOR, _ADD, _BITOP3: v_xor_b32, v_add_u32, v_bitop3_b32, in
  *     32-bit lane-ops per second (64 per wave instruction);
- *   SA_PEAK_CVT_FP4: v_cvt_scalef32_pk_fp4_f32 (2 floats to 2 fp4 codes),
- *     wave instructions x 64 per second;
+ *   SA_PEAK_CVT_FP4: v_cvt_scalef32_pk_fp4_f32 (2 floats to 2 fp4 codes per
+ *     lane), in values converted per second;
  *   SA_PEAK_MFMA_FP4: the unscaled fp4 x fp4 16x16x128 matrix product, in
- *     flops per second (2 x 16 x 16 x 128 per instruction).
+ *     flops per second (2 x 16 x 16 x 128 per instruction);
+ *   SA_PEAK_CVT_FP6: v_cvt_scalef32_2xpk16_fp6_f32 (32 floats to 32 fp6
+ *     codes per lane), in values converted per second;
+ *   SA_PEAK_MFMA_FP4_FP6: the same product with the B operand read as fp6.
+ * (The last two price an fp6 state encoding against the fp4 one.)
  * rate (host) receives the rate; ms (host, nullable) the best of two timed
  * launches after a warm-up one.  Allocates a small buffer, synchronises
  * `stream`. */
 enum { SA_PEAK_VALU_XOR = 0, SA_PEAK_VALU_ADD = 1, SA_PEAK_VALU_BITOP3 = 2, SA_PEAK_CVT_FP4 = 3,
-       SA_PEAK_MFMA_FP4 = 4 };
+       SA_PEAK_MFMA_FP4 = 4, SA_PEAK_CVT_FP6 = 5, SA_PEAK_MFMA_FP4_FP6 = 6 };
 int sa_measure_peak(int32_t kind, double *rate, double *ms, void *stream);
 
 /* Message of the last failure on the calling thread ("" if none). */

@@ -86,6 +86,12 @@ struct sa_run {
   std::vector<hipEvent_t> ev_start, ev_stop;  // per stage, when record_times is set
   std::vector<hipGraphExec_t> graphs;
   hipStream_t capture_stream = nullptr;  // private stream the stages are captured on
+  // persistent kernel with several launch groups: the groups of a stage run
+  // concurrently, group k > 0 on side[k - 1], forked from and joined to the
+  // launch stream with events (so one group's drain tail overlaps the others)
+  std::vector<hipStream_t> side;
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> join;
   bool learned = false;                  // learned proposal or trace: the learned-stage kernel
   sa::LearnedArgs la{};                  // its stage-independent part
   std::vector<float> lt;                 // per stage: f32(ln(T_k) / 5)
@@ -570,6 +576,9 @@ static void free_run(sa_run *r) {
   for (hipEvent_t e : r->ev_stop) hipEventDestroy(e);
   for (hipGraphExec_t g : r->graphs) hipGraphExecDestroy(g);
   if (r->capture_stream) hipStreamDestroy(r->capture_stream);
+  for (hipStream_t x : r->side) hipStreamDestroy(x);
+  if (r->fork) hipEventDestroy(r->fork);
+  for (hipEvent_t x : r->join) hipEventDestroy(x);
   hipFree(r->x0);
   hipFree(r->xbest);
   hipFree(r->xwin);
@@ -684,7 +693,14 @@ static int enqueue_stage(sa_run *r, int32_t st, hipStream_t stream, bool control
       }
     }
   } else {
-    for (size_t k = 0; k < r->item_class_d.size(); ++k) {
+    const size_t groups = r->item_class_d.size();
+    const bool fork = groups > 1 && r->side.size() + 1 >= groups;
+    if (fork) {
+      SA_HIP(hipEventRecord(r->fork, stream), "fork event");
+      for (size_t k = 1; k < groups; ++k) SA_HIP(hipStreamWaitEvent(r->side[k - 1], r->fork, 0), "fork wait");
+    }
+    for (size_t k = 0; k < groups; ++k) {
+      hipStream_t gs = fork && k > 0 ? r->side[k - 1] : stream;
       sa::BatchArgs a{};
       a.probs = r->probs_dev;
       a.n_probs = np;
@@ -710,9 +726,14 @@ static int enqueue_stage(sa_run *r, int32_t st, hipStream_t stream, bool control
       a.stop = stop;
       const int grid = std::max(1, std::min(a.n_items, r->cus * r->blocks_per_cu[k]));
       SA_HIP((hipError_t)sa::launch_persistent(a, r->item_class_cls[k], r->item_class_d[k], grid, r->class_smem[k],
-                                               stream),
+                                               gs),
              "persistent launch");
     }
+    if (fork)
+      for (size_t k = 1; k < groups; ++k) {
+        SA_HIP(hipEventRecord(r->join[k - 1], r->side[k - 1]), "join event");
+        SA_HIP(hipStreamWaitEvent(stream, r->join[k - 1], 0), "join wait");
+      }
   }
   if (timed) SA_HIP(hipEventRecord(r->ev_stop[st], stream), "event record");
   sa::BatchReduceArgs ra{};
@@ -1006,10 +1027,26 @@ extern "C" int sa_run_create(sa_problem *const *probs, int32_t n_probs, const sa
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
       r->cus = cus;
     int rc = SA_OK;
-    if (desc->chains_per_block == 0 && S > 0)
-      rc = autotune_waves(r, s);
-    else
-      rc = upload_items(r, desc->chains_per_block ? desc->chains_per_block : 4);
+    {
+      // side streams and events for the concurrent launch groups (default priority)
+      std::vector<int32_t> net, chain0;
+      build_items(r, 4, net, chain0);
+      const size_t groups = r->item_class_d.size();
+      hipError_t ce = hipSuccess;
+      if (groups > 1) ce = hipEventCreateWithFlags(&r->fork, hipEventDisableTiming);
+      for (size_t k = 1; k < groups && ce == hipSuccess; ++k) {
+        hipStream_t x = nullptr;
+        hipEvent_t j = nullptr;
+        ce = hipStreamCreateWithFlags(&x, hipStreamNonBlocking);
+        if (ce == hipSuccess) r->side.push_back(x);
+        if (ce == hipSuccess) ce = hipEventCreateWithFlags(&j, hipEventDisableTiming);
+        if (ce == hipSuccess) r->join.push_back(j);
+      }
+      if (ce != hipSuccess) rc = hip_fail(ce, "side streams");
+    }
+    if (rc == SA_OK)
+      rc = desc->chains_per_block == 0 && S > 0 ? autotune_waves(r, s)
+                                                : upload_items(r, desc->chains_per_block ? desc->chains_per_block : 4);
     if (rc == SA_OK) {
       const size_t lds_max = 160 * 1024;
       for (size_t smem : r->class_smem)
@@ -1202,7 +1239,7 @@ extern "C" int sa_destroy_run(sa_run *r) {
 // ---------------------------------------------------------------------------
 extern "C" int sa_measure_peak(int32_t kind, double *rate, double *ms_out, void *stream) {
   if (!rate) return fail(SA_ERR_ARG, "rate is NULL");
-  if (kind < SA_PEAK_VALU_XOR || kind > SA_PEAK_MFMA_FP4) return fail(SA_ERR_ARG, "unknown peak kind %d", kind);
+  if (kind < SA_PEAK_VALU_XOR || kind > SA_PEAK_MFMA_FP4_FP6) return fail(SA_ERR_ARG, "unknown peak kind %d", kind);
   hipStream_t s = (hipStream_t)stream;
   int dev = 0, cus = 0;
   SA_HIP(hipGetDevice(&dev), "hipGetDevice");

@@ -47,17 +47,45 @@ __global__ __launch_bounds__(256) void probe_valu_kernel(uint32_t *sink, int ite
   if (x == never) sink[blockIdx.x * blockDim.x + threadIdx.x] = x;
 }
 
+typedef int v6i __attribute__((ext_vector_type(6)));
 typedef int v8i __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+// The 32-value fp6 packing conversion (two groups of 16 float32 registers to
+// 6 dwords of fp6 codes): 8 conversions per loop trip from two register sets,
+// one xor of a result each keeps them alive.
+__global__ __launch_bounds__(256) void probe_cvt_fp6_kernel(uint32_t *sink, int iters, uint32_t never) {
+  v16f a[2], b[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      a[j][i] = (float)((threadIdx.x + i + j) & 7) - 3.f;
+      b[j][i] = (float)((threadIdx.x * i + j) & 5) - 2.f;
+    }
+  uint32_t acc = 0;
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const v6i x = __builtin_amdgcn_cvt_scalef32_2xpk16_fp6_f32(a[r & 1], b[r & 1], 0.25f);
+      acc ^= (uint32_t)x[r % 6];
+      asm volatile("" : "+v"(a[r & 1]), "+v"(b[r & 1]));
+    }
+  }
+  if (acc == never) sink[blockIdx.x * blockDim.x + threadIdx.x] = acc;
+}
 
 // Dense fp4 (e2m1) x fp4 products of the unscaled 16x16x128 form, the
-// instruction the annealing kernels run: 8 independent accumulators per wave.
-__global__ __launch_bounds__(256) void probe_mfma_fp4_kernel(float *sink, int iters, float never) {
+// instruction the annealing kernels run: 8 independent accumulators per wave
+// (FP6: the B operand read as fp6 e2m3 instead).
+template <bool FP6>
+__global__ __launch_bounds__(256) void probe_mfma_kernel(float *sink, int iters, float never) {
   v8i a = {}, b = {};
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < 6; ++j) {
     a[j] = (int)(0x22222222u + threadIdx.x + j);
-    b[j] = (int)(0x44444444u - threadIdx.x - j);
+    b[j] = (int)(0x04104104u - threadIdx.x - j);
   }
   v4f acc[kProbeChains];
 #pragma unroll
@@ -67,7 +95,8 @@ __global__ __launch_bounds__(256) void probe_mfma_fp4_kernel(float *sink, int it
     for (int r = 0; r < kProbeUnroll; ++r)
 #pragma unroll
       for (int j = 0; j < kProbeChains; ++j)
-        acc[j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, acc[j], 4, 4, 0, 0, 0, 0);
+        acc[j] = FP6 ? __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, acc[j], 4, 2, 0, 0, 0, 0)
+                     : __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, acc[j], 4, 4, 0, 0, 0, 0);
   }
   float x = 0.f;
 #pragma unroll
@@ -77,11 +106,28 @@ __global__ __launch_bounds__(256) void probe_mfma_fp4_kernel(float *sink, int it
 
 }  // namespace
 
-int probe_iters(int kind) { return kind == SA_PEAK_MFMA_FP4 ? 1024 : kind == SA_PEAK_CVT_FP4 ? 2048 : 8192; }
+int probe_iters(int kind) {
+  switch (kind) {
+    case SA_PEAK_MFMA_FP4:
+    case SA_PEAK_MFMA_FP4_FP6:
+      return 1024;
+    case SA_PEAK_CVT_FP4:
+      return 2048;
+    case SA_PEAK_CVT_FP6:
+      return 256;
+    default:
+      return 8192;
+  }
+}
 
+// Work of one launch: lane-ops (VALU), values converted (conversions), flops
+// (matrix products).
 double probe_work(int kind, int blocks, int threads) {
-  const double instr = (double)blocks * (threads / 64) * probe_iters(kind) * kProbeUnroll * kProbeChains;
-  return instr * (kind == SA_PEAK_MFMA_FP4 ? 2.0 * 16 * 16 * 128 : 64.0);
+  const double waves = (double)blocks * (threads / 64);
+  if (kind == SA_PEAK_CVT_FP6) return waves * probe_iters(kind) * 8 * 64 * 32.0;
+  const double instr = waves * probe_iters(kind) * kProbeUnroll * kProbeChains;
+  if (kind == SA_PEAK_MFMA_FP4 || kind == SA_PEAK_MFMA_FP4_FP6) return instr * 2.0 * 16 * 16 * 128;
+  return instr * 64.0 * (kind == SA_PEAK_CVT_FP4 ? 2.0 : 1.0);
 }
 
 int launch_probe(int kind, void *sink, int blocks, int threads, void *stream) {
@@ -102,8 +148,14 @@ int launch_probe(int kind, void *sink, int blocks, int threads, void *stream) {
     case SA_PEAK_CVT_FP4:
       probe_valu_kernel<SA_PEAK_CVT_FP4><<<blocks, threads, 0, s>>>(u, iters, k0, k1, never);
       break;
+    case SA_PEAK_CVT_FP6:
+      probe_cvt_fp6_kernel<<<blocks, threads, 0, s>>>(u, iters, never);
+      break;
     case SA_PEAK_MFMA_FP4:
-      probe_mfma_fp4_kernel<<<blocks, threads, 0, s>>>(static_cast<float *>(sink), iters, -1.0e30f);
+      probe_mfma_kernel<false><<<blocks, threads, 0, s>>>(static_cast<float *>(sink), iters, -1.0e30f);
+      break;
+    case SA_PEAK_MFMA_FP4_FP6:
+      probe_mfma_kernel<true><<<blocks, threads, 0, s>>>(static_cast<float *>(sink), iters, -1.0e30f);
       break;
     default:
       return (int)hipErrorInvalidValue;

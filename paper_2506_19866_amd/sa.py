@@ -33,6 +33,7 @@ EXPORTS = ("sa_create_problem", "sa_destroy_problem", "sa_problem_get_info", "sa
            "sa_mlp_destroy", "sa_mlp_get_params", "sa_mlp_set_params", "sa_mlp_forward", "sa_mlp_gradients",
            "sa_mlp_train_step", "sa_measure_peak", "sa_last_error")
 SA_PEAK_VALU_XOR, SA_PEAK_VALU_ADD, SA_PEAK_VALU_BITOP3, SA_PEAK_CVT_FP4, SA_PEAK_MFMA_FP4 = 0, 1, 2, 3, 4
+SA_PEAK_CVT_FP6, SA_PEAK_MFMA_FP4_FP6 = 5, 6
 MLP_INPUTS, MLP_HIDDEN = 32, 256
 MLP_N_PARAMS = MLP_INPUTS * MLP_HIDDEN + MLP_HIDDEN + 1
 
@@ -441,8 +442,9 @@ def bf16_bits_to_float(bits) -> np.ndarray:
 
 def measure_peak(kind: int, stream=None) -> tuple[float, float]:
     """Measured device-wide rate of one instruction kind (SA_PEAK_*): 32-bit
-    lane-ops per second for the VALU kinds and the packing conversion, flops
-    per second for the fp4 matrix product; and the timed launch's ms."""
+    lane-ops per second for the VALU kinds, values converted per second for
+    the packing conversions, flops per second for the matrix products; and
+    the timed launch's ms."""
     rate, ms = C.c_double(), C.c_double()
     _check(lib().sa_measure_peak(int(kind), C.byref(rate), C.byref(ms), _stream_handle(stream)))
     return rate.value, ms.value
