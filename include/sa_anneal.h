@@ -298,6 +298,34 @@ int sa_stage_times(sa_run *run, int32_t prob, float *ms_host);
 
 int sa_destroy_run(sa_run *run);
 
+/* The whole schedule of one problem without any device allocation: for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  Same method, kernels
+ * and results as sa_run_chains with that desc: bit for bit the same best
+ * vector, cost, winner and stage statistics.  The run's state (chain bests,
+ * costs, statistics, thresholds, stage records) lives in one fixed device
+ * array of SA_NOALLOC_SCRATCH_BYTES per GPU, held from the library's load to
+ * the end of the process, shared by every call on that GPU: calls that overlap
+ * on one GPU (other streams, other host threads) race and give wrong results.
+ * Nothing in it needs clearing: every stage writes all of its state before
+ * reading it.  Supports the specialised kernel with plain proposals and the
+ * global restart (kernel SA_KERNEL_AUTO, proposal SA_PROPOSAL_PLAIN,
+ * group_size 0 or >= n_chains, no trace, record_times, use_graph or
+ * abort_flag_host; else SA_ERR_UNSUPPORTED), n_stages >= 1, and runs needing
+ * at most SA_NOALLOC_SCRATCH_BYTES: 256-byte aligned blocks of 48 bytes per
+ * stage, n_chains * (P + 24) bytes, P bytes and the thresholds (4 bytes per
+ * entry, at most 46 per stage for T <= 2); e.g. 16384 chains of a
+ * 723-parameter problem need 12.3 MB.  Larger runs: SA_ERR_UNSUPPORTED, before
+ * any device work.
+ * x0_dev (device) [n_chains * P] starting vectors, read while the run is
+ * queued; x_best_dev (device) [P] receives the global best vector,
+ * best_dev (device) [2] its cost and chain, stats_dev (device, nullable)
+ * [n_stages] the stage statistics (sa_stage_stats layout).  Checks the
+ * starting vectors as sa_run_create does and synchronises `stream` for that;
+ * the stages are then queued on `stream` and the call returns. */
+#define SA_NOALLOC_SCRATCH_BYTES (16u << 20)
+int sa_run_chains_noalloc(const sa_problem *prob, const sa_run_desc *desc, const int8_t *x0_dev,
+                          int8_t *x_best_dev, int32_t *best_dev, sa_stage_stats *stats_dev, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Learned proposal network.  An extension of Table 1's GetCandidate (not in

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1231,6 +1232,158 @@ extern "C" int sa_destroy_run(sa_run *r) {
   hipSetDevice(r->device);
   hipStreamSynchronize(r->stream);
   free_run(r);
+  return SA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// the run without allocations (sa_run_chains_noalloc)
+// ---------------------------------------------------------------------------
+// The run state lives in this fixed device array instead of hipMalloc'ed
+// memory.  Host code never uses the array's name as an address: each device's
+// copy is looked up once with hipGetSymbolAddress (with that device current)
+// and that pointer is what the kernels get.
+static constexpr size_t kNoAllocScratchBytes = (size_t)SA_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+static constexpr int kMaxDevices = 64;
+static void *g_scratch_ptr[kMaxDevices];
+static hipError_t g_scratch_err[kMaxDevices];
+static std::once_flag g_scratch_once[kMaxDevices];
+
+static int scratch_for_device(int device, uint8_t *&ptr) {
+  if (device < 0 || device >= kMaxDevices) return fail(SA_ERR_UNSUPPORTED, "device %d beyond %d", device, kMaxDevices);
+  std::call_once(g_scratch_once[device], [device] {
+    g_scratch_err[device] = hipGetSymbolAddress(&g_scratch_ptr[device], HIP_SYMBOL(scratch));
+  });
+  if (g_scratch_err[device] != hipSuccess) return hip_fail(g_scratch_err[device], "hipGetSymbolAddress(scratch)");
+  if (!g_scratch_ptr[device]) return fail(SA_ERR_DEVICE, "no scratch address on device %d", device);
+  ptr = static_cast<uint8_t *>(g_scratch_ptr[device]);
+  return SA_OK;
+}
+
+static_assert(sizeof(sa_stage_stats) == sizeof(sa::StageRecord) && offsetof(sa_stage_stats, accepted) ==
+                  offsetof(sa::StageRecord, accepted) && offsetof(sa_stage_stats, simulated) ==
+                  offsetof(sa::StageRecord, simulated),
+              "stage statistics layout");
+
+extern "C" int sa_run_chains_noalloc(const sa_problem *prob, const sa_run_desc *desc, const int8_t *x0_dev,
+                                     int8_t *x_best_dev, int32_t *best_dev, sa_stage_stats *stats_dev,
+                                     void *stream) {
+  if (!prob || !desc || !x0_dev || !x_best_dev || !best_dev) return fail(SA_ERR_ARG, "NULL argument");
+  if (desc->n_chains < 1 || desc->n_chains > (1ll << 31) - 1) return fail(SA_ERR_ARG, "n_chains out of range");
+  if (!(desc->T0 > 0) || !(desc->rho > 0)) return fail(SA_ERR_ARG, "T0 and rho must be > 0");
+  if (desc->first_stage < 0 || desc->n_stages < 1 || desc->steps_per_stage < 1)
+    return fail(SA_ERR_ARG, "stage counts out of range (at least one stage)");
+  if (desc->kernel != SA_KERNEL_AUTO || desc->proposal != SA_PROPOSAL_PLAIN || desc->trace_dev ||
+      desc->record_times || desc->use_graph || desc->abort_flag_host || desc->group_size < 0 ||
+      (desc->group_size > 0 && desc->group_size < desc->n_chains))
+    return fail(SA_ERR_UNSUPPORTED, "the allocation-free run takes plain proposals, the global restart and the "
+                                    "specialised kernel, without trace, timing, graph or abort flag");
+  const sa::DevProblem &dp = prob->dev;
+  const int64_t n = desc->n_chains, P = dp.P;
+  const int S = desc->n_stages;
+  hipStream_t s = (hipStream_t)stream;
+  SA_HIP(hipSetDevice(prob->device), "hipSetDevice");
+  if (dp.model == SA_MODEL_PRIORITY) {
+    if (sa::priority_stage_smem_bytes(dp) > 64 * 1024)
+      return fail(SA_ERR_UNSUPPORTED, "priority stage kernel needs more than 64 KiB of LDS");
+  } else if (sa::stage_smem_bytes(dp, sa::stage_waves_per_block(dp)) > 64 * 1024) {
+    return fail(SA_ERR_UNSUPPORTED, "stage kernel needs more than 64 KiB of LDS");
+  }
+
+  // thresholds of every stage (host), as sa_run_create
+  std::vector<uint32_t> all_tau, tab;
+  std::vector<size_t> tau_off;
+  std::vector<int32_t> dcap;
+  double T = desc->T0;
+  for (int k = 0; k < desc->first_stage; ++k) T = T * desc->rho;
+  for (int st = 0; st < S; ++st) {
+    int32_t cap;
+    tau_table(T, prob->info.max_cost, tab, cap);
+    tau_off.push_back(all_tau.size());
+    dcap.push_back(cap);
+    all_tau.insert(all_tau.end(), tab.begin(), tab.end());
+    T = T * desc->rho;
+  }
+  // scratch layout: problem descriptor, offsets, thresholds, stage records,
+  // chain bests, winner, chain costs and statistics (256-byte aligned)
+  Layout lay;
+  const size_t o_dp = lay.take(sizeof(sa::DevProblem)), o_xoff = lay.take(8), o_woff = lay.take(8),
+               o_tau = lay.take(all_tau.size() * 4), o_rec = lay.take((size_t)S * sizeof(sa::StageRecord)),
+               o_xbest = lay.take((size_t)(n * P)), o_xwin = lay.take((size_t)P), o_cbest = lay.take((size_t)n * 4),
+               o_cstats = lay.take((size_t)n * 4 * sa::kStatWords);
+  if (lay.bytes > kNoAllocScratchBytes)
+    return fail(SA_ERR_UNSUPPORTED, "the run needs %zu bytes of scratch, more than the %zu the allocation-free "
+                                    "entry point has", lay.bytes, kNoAllocScratchBytes);
+  uint8_t *base = nullptr;
+  if (int rc = scratch_for_device(prob->device, base)) return rc;
+
+  // starting vectors: domain on the host
+  std::vector<int8_t> hx((size_t)(n * P));
+  SA_HIP(hipMemcpyAsync(hx.data(), x0_dev, hx.size(), hipMemcpyDeviceToHost, s), "copy x0");
+  SA_HIP(hipStreamSynchronize(s), "stream sync");
+  for (int64_t c = 0; c < n; ++c)
+    for (int k = 0; k < P; ++k)
+      if (!in_domain(dp, k, hx[(size_t)(c * P + k)]))
+        return fail(SA_ERR_DOMAIN, "x0 chain %lld parameter %d = %d", (long long)c, k, hx[(size_t)(c * P + k)]);
+  // the small tables, staged in one host block and copied in one call; the
+  // stream is synchronised below, before the block goes out of scope
+  std::vector<uint8_t> head(o_tau + all_tau.size() * 4);
+  const int64_t zero = 0;
+  std::memcpy(head.data() + o_dp, &dp, sizeof(dp));
+  std::memcpy(head.data() + o_xoff, &zero, 8);
+  std::memcpy(head.data() + o_woff, &zero, 8);
+  if (!all_tau.empty()) std::memcpy(head.data() + o_tau, all_tau.data(), all_tau.size() * 4);
+  SA_HIP(hipMemcpyAsync(base, head.data(), head.size(), hipMemcpyHostToDevice, s), "copy run tables");
+  int32_t *cbest = reinterpret_cast<int32_t *>(base + o_cbest);
+  uint32_t *cstats = reinterpret_cast<uint32_t *>(base + o_cstats);
+  if (dp.hard) {
+    // hard mode: every start satisfies (a) and (b) iff its cost equals its mismatch (lambda = 0)
+    sa::DevProblem m = dp;
+    m.lambda = 0;
+    SA_HIP((hipError_t)launch_cost(dp, x0_dev, n, cbest, s), "start costs");
+    SA_HIP((hipError_t)launch_cost(m, x0_dev, n, reinterpret_cast<int32_t *>(cstats), s), "start costs");
+    std::vector<int32_t> h1((size_t)n), h0((size_t)n);
+    SA_HIP(hipMemcpyAsync(h1.data(), cbest, (size_t)n * 4, hipMemcpyDeviceToHost, s), "copy costs");
+    SA_HIP(hipMemcpyAsync(h0.data(), cstats, (size_t)n * 4, hipMemcpyDeviceToHost, s), "copy costs");
+    SA_HIP(hipStreamSynchronize(s), "stream sync");
+    for (int64_t c = 0; c < n; ++c)
+      if (h1[(size_t)c] != h0[(size_t)c])
+        return fail(SA_ERR_INFEASIBLE, "x0 chain %lld breaks a structural constraint", (long long)c);
+  } else {
+    SA_HIP(hipStreamSynchronize(s), "stream sync");
+  }
+
+  // a run whose device state points into the scratch array; enqueue_stage
+  // queues exactly the kernels of sa_run_launch's eager path
+  sa_run r;
+  r.probs.assign(1, const_cast<sa_problem *>(prob));
+  r.desc = *desc;
+  r.device = prob->device;
+  r.n = n;
+  r.stream = s;
+  r.x0 = const_cast<int8_t *>(x0_dev);
+  r.xbest = reinterpret_cast<int8_t *>(base + o_xbest);
+  r.xwin = reinterpret_cast<int8_t *>(base + o_xwin);
+  r.cbest = cbest;
+  r.cstats = cstats;
+  r.tau = reinterpret_cast<uint32_t *>(base + o_tau);
+  r.rec = reinterpret_cast<sa::StageRecord *>(base + o_rec);
+  r.probs_dev = reinterpret_cast<sa::DevProblem *>(base + o_dp);
+  r.x_off_dev = reinterpret_cast<int64_t *>(base + o_xoff);
+  r.w_off_dev = reinterpret_cast<int64_t *>(base + o_woff);
+  r.x_off.assign(1, 0);
+  r.w_off.assign(1, 0);
+  r.tau_off = tau_off;
+  r.dcap = dcap;
+  for (int st = 0; st < S; ++st)
+    if (int rc = enqueue_stage(&r, st, s)) return rc;
+  SA_HIP(hipMemcpyAsync(x_best_dev, r.xwin, (size_t)P, hipMemcpyDeviceToDevice, s), "copy best vector");
+  SA_HIP(hipMemcpyAsync(best_dev, r.rec + (S - 1), 2 * sizeof(int32_t), hipMemcpyDeviceToDevice, s),
+         "copy best cost");
+  if (stats_dev)
+    SA_HIP(hipMemcpyAsync(stats_dev, r.rec, (size_t)S * sizeof(sa::StageRecord), hipMemcpyDeviceToDevice, s),
+           "copy stage statistics");
   return SA_OK;
 }
 

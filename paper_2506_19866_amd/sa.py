@@ -29,7 +29,7 @@ TRACE_DTYPE = np.dtype([("features", "<u2", (32,)), ("param", "<i4"), ("value", 
 
 EXPORTS = ("sa_create_problem", "sa_destroy_problem", "sa_problem_get_info", "sa_eval_cost",
            "sa_simulate", "sa_run_create", "sa_run_launch", "sa_run_chains", "sa_best", "sa_stats",
-           "sa_chain_best", "sa_stage_times", "sa_run_get_info", "sa_run_stages_done", "sa_destroy_run", "sa_mlp_create",
+           "sa_chain_best", "sa_stage_times", "sa_run_get_info", "sa_run_stages_done", "sa_destroy_run", "sa_run_chains_noalloc", "sa_mlp_create",
            "sa_mlp_destroy", "sa_mlp_get_params", "sa_mlp_set_params", "sa_mlp_forward", "sa_mlp_gradients",
            "sa_mlp_train_step", "sa_measure_peak", "sa_last_error")
 SA_PEAK_VALU_XOR, SA_PEAK_VALU_ADD, SA_PEAK_VALU_BITOP3, SA_PEAK_CVT_FP4, SA_PEAK_MFMA_FP4 = 0, 1, 2, 3, 4
@@ -114,6 +114,7 @@ def lib():
         L.sa_stage_times.argtypes = [vp, C.c_int32, vp]
         L.sa_run_get_info.argtypes = [vp, C.POINTER(_RunInfo)]
         L.sa_run_stages_done.argtypes = [vp, C.POINTER(C.c_int32)]
+        L.sa_run_chains_noalloc.argtypes = [vp, C.POINTER(_RunDesc), vp, vp, vp, vp, vp]
         L.sa_destroy_run.argtypes = [vp]
         L.sa_mlp_create.argtypes = [vp, C.POINTER(vp)]
         L.sa_mlp_destroy.argtypes = [vp]
@@ -340,6 +341,43 @@ class Run:
             self.close()
         except Exception:
             pass
+
+
+NOALLOC_SCRATCH_BYTES = 16 << 20
+
+
+def run_chains_noalloc(problem: Problem, x0, x_best, best, stats=None, *, seed: int, T0: float, rho: float,
+                       n_stages: int, steps_per_stage: int, first_stage: int = 0, stream=None) -> None:
+    """sa_run_chains_noalloc: the whole schedule with the run state in the
+    library's fixed device array (no device allocation in the call).  x0: int8
+    CUDA tensor [n_chains, P]; outputs (CUDA tensors, written on the stream):
+    x_best int8 [P], best int32 [2] (cost, winner chain), stats uint8
+    [n_stages * 48] (sa_stage_stats records) or None."""
+    import torch
+    x0 = _device_tensor(x0, torch.int8, problem.n_params)
+    x_best = _device_tensor(x_best, torch.int8)
+    best = _device_tensor(best, torch.int32)
+    if x_best.numel() < problem.n_params or best.numel() < 2:
+        raise ValueError("x_best needs P entries and best 2")
+    sp = None
+    if stats is not None:
+        stats = _device_tensor(stats, torch.uint8)
+        if stats.numel() < n_stages * C.sizeof(_StageStats):
+            raise ValueError("stats needs n_stages * 48 bytes")
+        sp = stats.data_ptr()
+    d = _RunDesc(x0.shape[0], int(seed) & (2**64 - 1), float(T0), float(rho), int(first_stage), int(n_stages),
+                 int(steps_per_stage), 0, SA_KERNEL_AUTO, 0, 0, SA_PROPOSAL_PLAIN, 16, None, 0.1, None, 0, 1, 0,
+                 None)
+    _check(lib().sa_run_chains_noalloc(problem.handle, C.byref(d), C.c_void_p(x0.data_ptr()),
+                                       C.c_void_p(x_best.data_ptr()), C.c_void_p(best.data_ptr()),
+                                       C.c_void_p(sp) if sp else None, _stream_handle(stream)))
+
+
+def decode_stage_stats(raw: np.ndarray) -> dict:
+    """sa_stage_stats records (bytes) as arrays, like Run.stats()."""
+    arr = (_StageStats * (len(raw) // C.sizeof(_StageStats))).from_buffer_copy(np.ascontiguousarray(raw).tobytes())
+    return {k: np.array([getattr(a, k) for a in arr], dtype=np.int64 if k in ("best_cost", "winner") else np.uint64)
+            for k, _ in _StageStats._fields_}
 
 
 def pack_mlp_params(W1, w2, b2) -> np.ndarray:
