@@ -109,9 +109,16 @@ __global__ __launch_bounds__(kBlock) void pr_stage_kernel(DevProblem pb, StageAr
   // pays for the bookkeeping in every time step.
   constexpr bool kTrackActs = LC == 64;
   uint32_t acur = kPrTold | kPrReady | kPrFar | kPrVisited;
+  // The range of this lane's node's image over the current trajectory (one
+  // chain per wave), widened by [lo, hi] when a candidate that moved it
+  // within saturation is accepted without a simulation, and recomputed by
+  // every simulation that is accepted.
+  PrImageRange rcur;
+  rcur.lo = -kPrNoImage;
+  rcur.hi = kPrNoImage;
   // Table 1: every stage starts by scoring the vector it restarts from
   int mcur = seg_sum<LC>(pr_mismatch<LC, DMAX, false>(pb, li, base, nd, ad, lstart, lobs, nullptr,
-                                                      kTrackActs ? &acur : nullptr));
+                                                      kTrackActs ? &acur : nullptr, kTrackActs ? &rcur : nullptr));
   int ccur = mcur + pb.lambda * vcur;
   int cbest = ccur;
   uint32_t n_acc = 0, n_up = 0, n_neu = 0, n_inf = 0, n_sim = 1;
@@ -140,6 +147,7 @@ __global__ __launch_bounds__(kBlock) void pr_stage_kernel(DevProblem pb, StageAr
       const bool mine = li == target;
       int slot = 0, src = 0, w0 = 0, p0 = 0, t0 = 0;
       bool moves = false;  // this lane's node can behave differently under the candidate
+      int dlo = 0, dhi = 0;  // change of the node's image where it changes within saturation
       if (blk < 3) {
         slot = e - pb.in_ptr[target];
         src = pb.edge_src[e];
@@ -156,8 +164,23 @@ __global__ __launch_bounds__(kBlock) void pr_stage_kernel(DevProblem pb, StageAr
           // an edge whose contribution (s div t) * w * p stays the same for
           // every state its source takes (w or p zero before and after, or a
           // source that never leaves 0) leaves every image unchanged
-          const uint32_t diff = pr_edge_table(w, pol, t) ^ pr_edge_table(w0, p0, t0);
-          moves = ((diff & 0x0000ff00u) && (seen & 0x00000100u)) || ((diff & 0x00ff0000u) && (seen & 0x00010000u));
+          const uint32_t tn = pr_edge_table(w, pol, t), to = pr_edge_table(w0, p0, t0), diff = tn ^ to;
+          const bool at1 = (diff & 0x0000ff00u) && (seen & 0x00000100u);
+          const bool at2 = (diff & 0x00ff0000u) && (seen & 0x00010000u);
+          moves = at1 || at2;
+          if (kTrackActs && moves) {
+            // the image changes by d1 where the source is 1 and d2 where it
+            // is 2; if it stays saturated at every step where the node is
+            // free, no goal changes
+            const int d1 = at1 ? (int)(int8_t)(tn >> 8) - (int)(int8_t)(to >> 8) : 0;
+            const int d2 = at2 ? (int)(int8_t)(tn >> 16) - (int)(int8_t)(to >> 16) : 0;
+            const int lo = min(0, min(d1, d2)), hi = max(0, max(d1, d2));
+            if (rcur.lo + lo >= 2 || rcur.hi + hi <= 0) {
+              moves = false;
+              dlo = lo;
+              dhi = hi;
+            }
+          }
         }
       } else if (mine) {
         // a node never eligible ignores its speed, one never told its memory
@@ -181,13 +204,20 @@ __global__ __launch_bounds__(kBlock) void pr_stage_kernel(DevProblem pb, StageAr
       const bool feasible = !(pb.hard && vc > 0);
       int mcand = mcur;
       uint32_t acand = acur;
+      PrImageRange rcand = rcur;
+      if (same_traj) {
+        rcand.lo += dlo;
+        rcand.hi += dhi;
+      }
       if (__builtin_amdgcn_ballot_w64(feasible && !same_traj) != 0) {
         uint32_t a = acur;
-        const int m = seg_sum<LC>(
-            pr_mismatch<LC, DMAX, false>(pb, li, base, nd, ad, lstart, lobs, nullptr, kTrackActs ? &a : nullptr));
+        PrImageRange r = rcur;
+        const int m = seg_sum<LC>(pr_mismatch<LC, DMAX, false>(pb, li, base, nd, ad, lstart, lobs, nullptr,
+                                                               kTrackActs ? &a : nullptr, kTrackActs ? &r : nullptr));
         if (!same_traj) {
           mcand = m;
           acand = a;
+          rcand = r;
         }
       }
       n_sim += feasible && !same_traj;
@@ -205,6 +235,7 @@ __global__ __launch_bounds__(kBlock) void pr_stage_kernel(DevProblem pb, StageAr
         vcur = vc;
         mcur = mcand;
         acur = acand;
+        rcur = rcand;
         ccur = ccand;
       }
       if (!accept && mine) {  // back to the current parameters

@@ -228,12 +228,23 @@ __device__ __forceinline__ int pr_image(const PrNode<LC, DMAX> &nd, const PrAddr
 // or 2 (bit 16), the only states in which its out-edges contribute.
 constexpr uint32_t kPrTold = 1, kPrReady = 2, kPrFar = 4, kPrVisited = 0x10100u;
 
+// Smallest and largest image K_i the node had at a step where it was free
+// (its goal clamp(K_i, 0, 2) mattered), over every condition and step of a
+// trajectory; kPrNoImage when it never was.  A change of K_i by at most
+// [lo, hi] (lo <= 0 <= hi) leaves every goal, and so the trajectory, as it is
+// when min + lo >= 2 or max + hi <= 0 (the image stays saturated).
+constexpr int kPrNoImage = 1 << 20;
+struct PrImageRange {
+  int lo = kPrNoImage, hi = -kPrNoImage;
+};
+
 template <int LC, int DMAX, bool TRAJ>
 __device__ __forceinline__ int pr_mismatch(const DevProblem &pb, int li, int base, const PrNode<LC, DMAX> &nd,
                                            const PrAddr<DMAX> &ad, const uint8_t *start, const uint32_t *obs,
-                                           int8_t *traj, uint32_t *act = nullptr) {
+                                           int8_t *traj, uint32_t *act = nullptr, PrImageRange *range = nullptr) {
   const int T = pb.T;
   int acc = 0;
+  int klo = kPrNoImage, khi = -kPrNoImage;
   bool told_any = false, ready_any = false, far_any = false;
   int vis = 0;
   for (int c = 0; c < pb.C; ++c) {
@@ -248,6 +259,10 @@ __device__ __forceinline__ int pr_mismatch(const DevProblem &pb, int li, int bas
     if (TRAJ && traj && li < pb.N) traj[(size_t)c * (T + 1) * pb.N + li] = (int8_t)s;
     for (int t = 1; t <= T; ++t) {
       const int img = pr_image<LC, DMAX>(nd, ad, s, oh, base);
+      if (range && inc) {
+        klo = min(klo, img);
+        khi = max(khi, img);
+      }
       const int goal = min(max(img, 0), 2);
       const bool told = inc && goal != s;
       idle += inc;
@@ -272,6 +287,10 @@ __device__ __forceinline__ int pr_mismatch(const DevProblem &pb, int li, int bas
   if (act)
     *act = (told_any ? kPrTold : 0u) | (ready_any ? kPrReady : 0u) | (far_any ? kPrFar : 0u) |
            ((uint32_t)vis & kPrVisited);
+  if (range) {
+    range->lo = klo;
+    range->hi = khi;
+  }
   return acc;
 }
 

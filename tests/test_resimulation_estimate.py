@@ -139,3 +139,57 @@ def test_priority_model_restart_from_first_affected_step():
               f"skip's share); the others first differ at step {np.mean(first):.2f} of {T}: a restart there would "
               f"skip {ideal:.3f} of their steps, one at the rule's first affected step {practical:.3f}")
         assert 0.0 <= practical <= ideal
+
+
+def test_priority_model_image_margin_skip_is_exact():
+    """The priority kernel's second exact skip: an edge j -> i whose change
+    alters node i's image K_i only at steps where K_i stays saturated
+    (min K_i + lo >= 2 or max K_i + hi <= 0 over the steps where i is free,
+    lo/hi the changes at the source states it takes) leaves every goal
+    clamp(K_i, 0, 2) (§2.1) and so the trajectory unchanged.  Checked here
+    against full simulations; prints the share of candidates it adds to the
+    contribution-table rule."""
+    w = synth.load_workload("q3")
+    o = OracleProblem(w)
+    E, N = w["n_edges"], w["n_nodes"]
+    src = w["src"]
+    dst = np.repeat(np.arange(N), np.diff(w["row_ptr"]))
+    T = int(np.max(w["obs_t"]))
+    free = w["clamp"] < 0                                   # [C][N]
+    doms = [(0, 2)] * E + [(-1, 1)] * E + [(1, 2)] * E
+    rng = np.random.default_rng(29)
+
+    def table(xv, e):
+        return np.array([(sv // int(xv[2 * E + e])) * int(xv[e]) * int(xv[E + e]) for sv in range(3)])
+    for label, x in _current_vectors("q3", w, o).items():
+        traj = o.simulate(x)[:, :T + 1, :].astype(np.int64)
+        K = np.zeros((traj.shape[0], T, N), dtype=np.int64)       # images at steps 1..T from states at 0..T-1
+        for e in range(E):
+            K[:, :, dst[e]] += (traj[:, :T, src[e]] // int(x[2 * E + e])) * int(x[e]) * int(x[E + e])
+        big = 1 << 20
+        kmin = np.where(free[:, None, :], K, big).min(axis=(0, 1))
+        kmax = np.where(free[:, None, :], K, -big).max(axis=(0, 1))
+        v0 = o.violations(x)
+        feasible = table_rule = margin_rule = 0
+        for _ in range(400):
+            i = int(rng.integers(0, 3 * E))
+            new = int(rng.choice([v for v in range(doms[i][0], doms[i][1] + 1) if v != int(x[i])]))
+            xc = x.copy()
+            xc[i] = new
+            if o.violations(xc) > v0:
+                continue
+            feasible += 1
+            e = i % E
+            d = table(xc, e) - table(x, e)
+            seen = np.unique(traj[:, :T, src[e]])
+            dv = [int(d[sv]) for sv in seen if d[sv] != 0]
+            if not dv:
+                table_rule += 1
+                continue
+            lo, hi = min(0, min(dv)), max(0, max(dv))
+            if kmin[dst[e]] + lo >= 2 or kmax[dst[e]] + hi <= 0:
+                margin_rule += 1
+                assert np.array_equal(o.simulate(xc)[:, :T + 1, :], traj), "margin rule skipped a changed trajectory"
+        print(f"q3 {label}: of {feasible} feasible edge candidates the table rule skips {table_rule / feasible:.3f}, "
+              f"the image-margin rule {margin_rule / feasible:.3f} more")
+        assert margin_rule > 0
