@@ -624,7 +624,8 @@ def main() -> int:
         model = (f"the paper's priority-update model, {prob['n_nodes']} nodes, {prob['n_edges']} edges, "
                  f"{P.n_params} params (w, p, t per edge; u, m, d per node)")
     else:
-        kernel = f"stage_kernel<{info['tiles_m']},{info['frags_k']},{int(prob.get('step_size', 1))}>"
+        hold = "false" if P.info["clamps_by_offset"] else "true"
+        kernel = f"stage_kernel<{info['tiles_m']},{info['frags_k']},{int(prob.get('step_size', 1))},{hold}>"
         traffic = traffic_from_profiles(launch_key)
         model = (f"Mtb-scale, {prob['n_nodes']} nodes, {prob['n_edges']} edges, {P.n_params} ternary params "
                  f"(synchronous update)")

@@ -263,6 +263,7 @@ static int create_priority(const sa_problem_desc *d, const std::vector<int> &W, 
   in.weight_sum = (int32_t)wsum;
   in.penalty = (int32_t)lambda;
   in.max_cost = (int32_t)max_cost;
+  in.clamps_by_offset = 0;
   *out = pr;
   return SA_OK;
 }
@@ -302,14 +303,44 @@ extern "C" int sa_create_problem(const sa_problem_desc *d, sa_problem **out) {
   if (CG > sa::kMaxCondGroups) return fail(SA_ERR_UNSUPPORTED, "n_conditions %d > 64", C);
 
   // slots: observed nodes first (their states then sit in the first dwords of
-  // every lane), round-robin over the four lane groups; bias after the nodes
+  // every lane), round-robin over the four lane groups; bias after the nodes.
+  // Clamped nodes go before them when that puts every clamped node in the
+  // first dword of every lane without lengthening the observed dwords and
+  // every clamp value is 0 or 2: the stage kernel then holds them by
+  // accumulator offsets of the first two m-tiles (DevProblem::cofs) and
+  // needs no per-dword select.
   std::vector<int> order, obs_index(N, -1);
-  for (int o = 0; o < O; ++o) {
-    order.push_back(d->obs_nodes[o]);
-    obs_index[d->obs_nodes[o]] = o;
+  for (int o = 0; o < O; ++o) obs_index[d->obs_nodes[o]] = o;
+  std::vector<char> clamped(N, 0);
+  bool values_02 = true;
+  for (int c = 0; c < C; ++c)
+    for (int v = 0; v < N; ++v) {
+      const int cl = d->clamp[(size_t)c * N + v];
+      clamped[v] |= cl >= 0;
+      values_02 = values_02 && cl != 1;
+    }
+  int n_clamped = 0, n_clamped_unobs = 0;
+  for (int v = 0; v < N; ++v) {
+    n_clamped += clamped[v];
+    n_clamped_unobs += clamped[v] && obs_index[v] < 0;
   }
-  for (int v = 0; v < N; ++v)
-    if (obs_index[v] < 0) order.push_back(v);
+  const bool hold_by_offset = values_02 && n_clamped <= 32 &&
+                              (n_clamped_unobs + O + 31) / 32 <= std::max(1, (O + 31) / 32);
+  if (hold_by_offset) {
+    // unobserved clamped, observed clamped, observed, the rest
+    for (int v = 0; v < N; ++v)
+      if (clamped[v] && obs_index[v] < 0) order.push_back(v);
+    for (int o = 0; o < O; ++o)
+      if (clamped[d->obs_nodes[o]]) order.push_back(d->obs_nodes[o]);
+    for (int o = 0; o < O; ++o)
+      if (!clamped[d->obs_nodes[o]]) order.push_back(d->obs_nodes[o]);
+    for (int v = 0; v < N; ++v)
+      if (!clamped[v] && obs_index[v] < 0) order.push_back(v);
+  } else {
+    for (int o = 0; o < O; ++o) order.push_back(d->obs_nodes[o]);
+    for (int v = 0; v < N; ++v)
+      if (obs_index[v] < 0) order.push_back(v);
+  }
   std::vector<int> sg(N), sq(N);
   const int slots = 32 * nk;
   std::vector<int16_t> slot_node((size_t)4 * slots, -1);
@@ -349,6 +380,21 @@ extern "C" int sa_create_problem(const sa_problem_desc *d, sa_problem **out) {
     std::vector<int32_t> fill(out_ptr.begin(), out_ptr.end() - 1);
     for (int e = 0; e < E; ++e) out_eid[fill[esrc[e]]++] = e;
   }
+
+  // accumulator offsets of m-tiles 0 and 1: [CG][2][64 lanes][4] (row 4g + r
+  // of m-tile mt in lane group g is slot q = 4 mt + r)
+  std::vector<float> cofs((size_t)CG * 2 * 64 * 4, 0.f);
+  for (int cg = 0; cg < CG && hold_by_offset; ++cg)
+    for (int mt = 0; mt < std::min(nm, 2); ++mt)
+      for (int lane = 0; lane < 64; ++lane) {
+        const int c = cg * 16 + lane % 16, g = lane / 16;
+        for (int r = 0; r < 4; ++r) {
+          const int v = slot_node[(size_t)g * slots + 4 * mt + r];
+          if (c >= C || v < 0) continue;
+          const int cl = d->clamp[(size_t)c * N + v];
+          cofs[(((size_t)cg * 2 + mt) * 64 + lane) * 4 + r] = cl == 2 ? 16384.f : cl == 0 ? -16384.f : 0.f;
+        }
+      }
 
   // per (condition group, dword, lane): initial states and the held-byte mask
   const int Q4 = 4 * nk;
@@ -429,7 +475,7 @@ extern "C" int sa_create_problem(const sa_problem_desc *d, sa_problem **out) {
   const size_t o_esrc = lay.take((size_t)E * 4), o_edst = lay.take((size_t)E * 4);
   const size_t o_inptr = lay.take((size_t)(N + 1) * 4), o_outptr = lay.take((size_t)(N + 1) * 4);
   const size_t o_outeid = lay.take((size_t)E * 4);
-  const size_t o_b0 = lay.take(b0.size() * 4), o_cm = lay.take(cm.size() * 4);
+  const size_t o_b0 = lay.take(b0.size() * 4), o_cm = lay.take(cm.size() * 4), o_cofs = lay.take(cofs.size() * 4);
   const size_t o_or = lay.take(orr.size() * 4), o_ow = lay.take(ow.size() * 4);
   const size_t o_obst = lay.take((size_t)K * 4), o_slot = lay.take(slot_node.size() * 2);
   const size_t o_nslot = lay.take((size_t)N * 2), o_nsw = lay.take((size_t)N * 4), o_nwr = lay.take((size_t)N * 4);
@@ -452,6 +498,7 @@ extern "C" int sa_create_problem(const sa_problem_desc *d, sa_problem **out) {
   put(o_outeid, out_eid.data(), (size_t)E * 4);
   put(o_b0, b0.data(), b0.size() * 4);
   put(o_cm, cm.data(), cm.size() * 4);
+  put(o_cofs, cofs.data(), cofs.size() * 4);
   put(o_or, orr.data(), orr.size() * 4);
   put(o_ow, ow.data(), ow.size() * 4);
   put(o_obst, d->obs_times, (size_t)K * 4);
@@ -481,6 +528,8 @@ extern "C" int sa_create_problem(const sa_problem_desc *d, sa_problem **out) {
   dp.out_eid = (const int32_t *)(base + o_outeid);
   dp.b0 = (const uint32_t *)(base + o_b0);
   dp.cmask = (const uint32_t *)(base + o_cm);
+  dp.cofs = (const float *)(base + o_cofs);
+  dp.hold_by_offset = hold_by_offset ? 1 : 0;
   dp.obs_r = (const uint32_t *)(base + o_or);
   dp.obs_w = (const uint32_t *)(base + o_ow);
   dp.obs_t = (const int32_t *)(base + o_obst);
@@ -497,6 +546,7 @@ extern "C" int sa_create_problem(const sa_problem_desc *d, sa_problem **out) {
   in.weight_sum = (int32_t)wsum;
   in.penalty = (int32_t)lambda;
   in.max_cost = (int32_t)max_cost;
+  in.clamps_by_offset = hold_by_offset ? 1 : 0;
   *out = pr;
   return SA_OK;
 }

@@ -39,7 +39,7 @@ struct NoHooks {
   static constexpr bool kEnabled = false;
 };
 
-template <int NM, int NK, int D, bool RT, class Hooks = NoHooks>
+template <int NM, int NK, int D, bool RT, class Hooks = NoHooks, bool HOLD = true>
 __device__ __forceinline__ void run_chain(const DevProblem &pb, const ChainJob &job, int lane, uint8_t *lds,
                                           const uint32_t *lds_r, const uint32_t *lds_w, Hooks *hk = nullptr) {
   const int P = pb.P, E = pb.E;
@@ -56,7 +56,7 @@ __device__ __forceinline__ void run_chain(const DevProblem &pb, const ChainJob &
   SA_DECLARE_A(A, NM, NK);
   build_a(A, pb, lane, xv);
   // Table 1: every stage starts by scoring the vector it restarts from
-  int ccur = uniform(wave_sum(lane_mismatch<NM, NK, D, false, RT>(A, pb, lane, lds_r, lds_w, nullptr))) +
+  int ccur = uniform(wave_sum(lane_mismatch<NM, NK, D, false, RT, HOLD>(A, pb, lane, lds_r, lds_w, nullptr))) +
              pb.lambda * vcur;
   int cbest = ccur;
   uint32_t n_acc = 0, n_up = 0, n_neu = 0, n_inf = 0;
@@ -108,7 +108,7 @@ __device__ __forceinline__ void run_chain(const DevProblem &pb, const ChainJob &
       patch_a(A, reg, mask, bits_new);
       int ccand = 0;
       if (feasible)
-        ccand = uniform(wave_sum(lane_mismatch<NM, NK, D, false, RT>(A, pb, lane, lds_r, lds_w, nullptr))) +
+        ccand = uniform(wave_sum(lane_mismatch<NM, NK, D, false, RT, HOLD>(A, pb, lane, lds_r, lds_w, nullptr))) +
                 pb.lambda * vc;
       const int delta = ccand - ccur;
       // Metropolis in fixed point: accept iff delta <= 0 or u32 < tau[delta]

@@ -339,9 +339,13 @@ __device__ __forceinline__ void write_states(const v4i (&B)[NK], const DevProble
 // old state as target, so they hold) and the step.  With RT only the first nm
 // m-tiles and nk k-fragments are present (a smaller network in a larger
 // layout).
-template <int NM, int NK, int D, bool RT>
+// HOLD: held nodes keep their state through a per-dword select with CM;
+// without HOLD, every clamped node is in the first dword, OF holds the
+// accumulator offsets of m-tiles 0 and 1 (clamped nodes forced to their
+// clamp value by the product, DevProblem::cofs) and no select is needed.
+template <int NM, int NK, int D, bool RT, bool HOLD = true>
 __device__ __forceinline__ void time_step(const ATile<NM, NK> &A, const v4i (&B)[NK], v4i (&NB)[NK],
-                                          const v4i (&CM)[NK], int nm, int nk) {
+                                          const v4i (&CM)[NK], int nm, int nk, const v4f *OF = nullptr) {
   v8i bw[NK];
 #pragma unroll
   for (int kf = 0; kf < NK; ++kf) bw[kf] = widen(B[kf]);
@@ -354,6 +358,7 @@ __device__ __forceinline__ void time_step(const ATile<NM, NK> &A, const v4i (&B)
       constexpr int h = decltype(hc)::value;
       constexpr int mt = 2 * w + h;
       acc[h] = v4f{0.f, 0.f, 0.f, 0.f};
+      if constexpr (!HOLD && mt < 2 && mt < NM) acc[h] = OF[mt];
       if constexpr (mt < NM) {
         if (!RT || mt < nm) {
           static_for<NK>([&](auto kc) SA_INLINE {
@@ -374,10 +379,18 @@ __device__ __forceinline__ void time_step(const ATile<NM, NK> &A, const v4i (&B)
       }
     });
     const uint32_t s = (uint32_t)B[kf][dw];
-    const uint32_t cm = (uint32_t)CM[kf][dw];
-    // cm ? s : next bitwise, one v_bitop3_b32 (truth table indexed by
-    // (next << 2) | (s << 1) | cm: set for 3, 4, 6, 7)
-    NB[kf][dw] = (int)__builtin_amdgcn_bitop3_b32(next_states<D>(x, s), s, cm, 0xD8);
+    if constexpr (HOLD) {
+      const uint32_t cm = (uint32_t)CM[kf][dw];
+      // cm ? s : next bitwise, one v_bitop3_b32 (truth table indexed by
+      // (next << 2) | (s << 1) | cm: set for 3, 4, 6, 7)
+      NB[kf][dw] = (int)__builtin_amdgcn_bitop3_b32(next_states<D>(x, s), s, cm, 0xD8);
+    } else if constexpr (2 * w + 1 >= NM) {
+      // the dword's second m-tile is beyond the layout: its nibbles (the bias
+      // slot when the node count is a multiple of 16, else empty slots) hold
+      NB[kf][dw] = (int)__builtin_amdgcn_bitop3_b32(next_states<D>(x, s), s, 0xFFFF0000u, 0xD8);
+    } else {
+      NB[kf][dw] = (int)next_states<D>(x, s);
+    }
   });
   // dwords without m-tile rows (slots beyond the rows) carry over unchanged
   static_for<4 * NK>([&](auto qc) SA_INLINE {
@@ -390,7 +403,7 @@ __device__ __forceinline__ void time_step(const ATile<NM, NK> &A, const v4i (&B)
 #pragma unroll
     for (int kf = 0; kf < NK; ++kf) asm volatile("" : "+v"(NB[kf]));
     // integer instructions per dword: 4 conversions, the update, the select
-    constexpr int kValu = D == 1 ? 11 : 10;
+    constexpr int kValu = (D == 1 ? 11 : 10) - (HOLD ? 0 : 1);
     __builtin_amdgcn_sched_group_barrier(0x008, 2 * NK, 0);
     static_for<NW - 1>([&](auto) SA_INLINE {
       __builtin_amdgcn_sched_group_barrier(0x008, 2 * NK, 0);
@@ -405,7 +418,7 @@ __device__ __forceinline__ void time_step(const ATile<NM, NK> &A, const v4i (&B)
 // [CG][K][nd][64] tables.  The two state buffers alternate between steps.
 // Without a trajectory to record, the simulation ends at the last observed
 // time (later states do not enter M).
-template <int NM, int NK, int D, bool TRAJ, bool RT = false>
+template <int NM, int NK, int D, bool TRAJ, bool RT = false, bool HOLD = true>
 __device__ __forceinline__ int lane_mismatch(const ATile<NM, NK> &A, const DevProblem &pb, int lane,
                                              const uint32_t *obs_r, const uint32_t *obs_w,
                                              int8_t *__restrict__ traj) {
@@ -413,6 +426,7 @@ __device__ __forceinline__ int lane_mismatch(const ATile<NM, NK> &A, const DevPr
   int total = 0;
   for (int cg = 0; cg < pb.CG; ++cg) {
     v4i B0[NK], B1[NK], CM[NK];
+    v4f OF[2];
     const int base = cg * 4 * nk;
 #pragma unroll
     for (int kt = 0; kt < NK; ++kt)
@@ -421,8 +435,13 @@ __device__ __forceinline__ int lane_mismatch(const ATile<NM, NK> &A, const DevPr
         const bool present = !RT || kt < nk;
         const int at = (base + kt * 4 + dw) * kWave + lane;
         B0[kt][dw] = present ? (int)pb.b0[at] : 0;
-        CM[kt][dw] = present ? (int)pb.cmask[at] : -1;
+        if constexpr (HOLD) CM[kt][dw] = present ? (int)pb.cmask[at] : -1;
       }
+    if constexpr (!HOLD) {
+      const v4f *of = reinterpret_cast<const v4f *>(pb.cofs) + (size_t)cg * 2 * kWave + lane;
+#pragma unroll
+      for (int mt = 0; mt < 2 && mt < NM; ++mt) OF[mt] = of[(size_t)mt * kWave];
+    }
     const int c = cg * 16 + (lane & 15);
     const uint32_t *rbase = obs_r + (size_t)cg * pb.K * pb.nd * kWave;
     const uint32_t *wbase = obs_w + (size_t)cg * pb.K * pb.nd * kWave;
@@ -440,13 +459,13 @@ __device__ __forceinline__ int lane_mismatch(const ATile<NM, NK> &A, const DevPr
     const int t_end = TRAJ ? pb.T : load_uniform(pb.obs_t, pb.K - 1);
     int t = 1;
     for (; t + 1 <= t_end; t += 2) {
-      time_step<NM, NK, D, RT>(A, B0, B1, CM, nm, nk);
+      time_step<NM, NK, D, RT, HOLD>(A, B0, B1, CM, nm, nk, OF);
       observe(B1, t);
-      time_step<NM, NK, D, RT>(A, B1, B0, CM, nm, nk);
+      time_step<NM, NK, D, RT, HOLD>(A, B1, B0, CM, nm, nk, OF);
       observe(B0, t + 1);
     }
     if (t <= t_end) {
-      time_step<NM, NK, D, RT>(A, B0, B1, CM, nm, nk);
+      time_step<NM, NK, D, RT, HOLD>(A, B0, B1, CM, nm, nk, OF);
       observe(B1, t);
     }
   }

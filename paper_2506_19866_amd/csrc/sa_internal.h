@@ -54,6 +54,18 @@ struct DevProblem {
   // at their clamp value) and the mask of nibbles that are held (clamped
   // nodes, the bias slot, empty slots and lanes beyond the last condition)
   const uint32_t *b0, *cmask;
+  // Where every clamp value is 0 or 2 and every clamped node sits in the
+  // first dword of every lane (hold_by_offset = 1), clamped nodes are held by
+  // the product itself instead: [CG][2 m-tiles][64 lanes][4] accumulator
+  // offsets of m-tiles 0 and 1, +2^14 for a row whose node is clamped to 2 in
+  // the lane's condition and -2^14 for one clamped to 0 (0 elsewhere), far
+  // beyond any |2(h - 1)| <= 4 in-degree + 6 (and exact in float32), so the
+  // node's target is its clamp value and it stays there; the bias row
+  // (all-zero A row: target 1), empty slots and unclamped nodes need no
+  // hold, except in the unused half of a layout's last dword, which keeps its
+  // state.
+  const float *cofs;
+  int32_t hold_by_offset;
   // [CG][K][nd dwords][64 lanes]: packed reference values and weights, a
   // nibble per slot (weight 0 where unobserved)
   const uint32_t *obs_r, *obs_w;

@@ -7,7 +7,9 @@ namespace sa {
 
 // LDS of a block: the observation tables shared by its chains, then one
 // chain area per wave.
-template <int NM, int NK, int D>
+// HOLD: clamped nodes held by a select per dword; otherwise by accumulator
+// offsets of the product (every clamp value 0 or 2, DevProblem::cofs).
+template <int NM, int NK, int D, bool HOLD>
 __global__ __launch_bounds__(256) void stage_kernel(DevProblem pb, StageArgs sa) {
   extern __shared__ uint32_t smem[];
   if (sa.stop && *sa.stop) return;  // the run was aborted at a stage boundary
@@ -36,7 +38,7 @@ __global__ __launch_bounds__(256) void stage_kernel(DevProblem pb, StageArgs sa)
   job.dcap = sa.dcap;
   job.tau = sa.tau;
   uint8_t *lds = reinterpret_cast<uint8_t *>(smem + 2 * n_obs) + (size_t)wv * chain_lds_bytes(pb);
-  run_chain<NM, NK, D, false>(pb, job, lane, lds, lds_r, lds_w);
+  run_chain<NM, NK, D, false, NoHooks, HOLD>(pb, job, lane, lds, lds_r, lds_w);
 }
 
 size_t stage_smem_bytes(const DevProblem &pb, int waves_per_block) {
@@ -50,10 +52,16 @@ int launch_stage(const DevProblem &pb, const StageArgs &sa, void *stream) {
   const size_t smem = stage_smem_bytes(pb, kWavesPerBlock);
 #define SA_CASE(M, K)                                                                         \
   case M:                                                                                     \
-    if (pb.d == 1)                                                                            \
-      stage_kernel<M, K, 1><<<grid_for(sa.n_chains), 256, smem, s>>>(pb, sa);                 \
-    else                                                                                      \
-      stage_kernel<M, K, 2><<<grid_for(sa.n_chains), 256, smem, s>>>(pb, sa);                 \
+    if (pb.hold_by_offset) {                                                                  \
+      if (pb.d == 1)                                                                          \
+        stage_kernel<M, K, 1, false><<<grid_for(sa.n_chains), 256, smem, s>>>(pb, sa);        \
+      else                                                                                    \
+        stage_kernel<M, K, 2, false><<<grid_for(sa.n_chains), 256, smem, s>>>(pb, sa);        \
+    } else if (pb.d == 1) {                                                                   \
+      stage_kernel<M, K, 1, true><<<grid_for(sa.n_chains), 256, smem, s>>>(pb, sa);           \
+    } else {                                                                                  \
+      stage_kernel<M, K, 2, true><<<grid_for(sa.n_chains), 256, smem, s>>>(pb, sa);           \
+    }                                                                                         \
     break;
   switch (pb.nm) {
     SA_FOR_TILES(SA_CASE)

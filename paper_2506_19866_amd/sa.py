@@ -61,7 +61,7 @@ class _ProblemDesc(C.Structure):
 class _ProblemInfo(C.Structure):
     _fields_ = [(k, C.c_int32) for k in (
         "n_params", "n_nodes", "n_edges", "n_conditions", "n_steps", "n_obs_times", "n_obs_nodes",
-        "weight_sum", "penalty", "max_cost")]
+        "weight_sum", "penalty", "max_cost", "clamps_by_offset")]
 
 
 class _RunDesc(C.Structure):

@@ -42,7 +42,7 @@ def from_edges(n_nodes, edges_src_dst, *, init, clamp=None, n_steps=5, obs_t=(1,
 
 
 def random_problem(seed, *, n_nodes, n_edges, n_cond, n_steps, n_times, n_obs, noise=0.0,
-                   clamps=(1, 1), step_size=1, hard=1, topology="cycle_plus_uniform"):
+                   clamps=(1, 1), step_size=1, hard=1, topology="cycle_plus_uniform", clamp_values=(0, 2)):
     """A seeded random problem whose reference data are the oracle trajectories
     of a hidden feasible vector (plus optional noise).  Returns (prob, hidden)."""
     from oracle.oracle import OracleProblem
@@ -54,7 +54,7 @@ def random_problem(seed, *, n_nodes, n_edges, n_cond, n_steps, n_times, n_obs, n
     else:
         row_ptr, src = synth.topology_bounded_indegree(rng, n_nodes, n_edges)
     hidden = synth.feasible_params(rng, 1, row_ptr, src)[0]
-    init, clamp = synth.conditions(rng, n_nodes, n_cond, clamps)
+    init, clamp = synth.conditions(rng, n_nodes, n_cond, clamps, clamp_values)
     obs_t = synth.observation_times(n_steps, n_times)
     obs_n = np.sort(rng.choice(n_nodes, size=n_obs, replace=False)).astype(np.int32)
     prob = dict(n_nodes=n_nodes, n_edges=n_edges, row_ptr=row_ptr, src=src, n_cond=n_cond,

@@ -182,6 +182,43 @@ def test_run_c2_truncated():
     _compare_runs(w, x0, s["seed"], T0=s["T0"], rho=s["rho"], n_stages=3, L=150)
 
 
+@pytest.mark.parametrize("N,E,C,d,values,clamps,O,by_offset", [
+    # clamp value 1 cannot be forced through the accumulator: select
+    (40, 130, 12, 1, (1,), (1, 3), 10, 0),
+    (120, 600, 16, 1, (0, 1, 2), (1, 3), 30, 0),
+    (90, 300, 20, 2, (1, 2), (1, 3), 22, 0),
+    # more than 32 clamped nodes: select
+    (120, 600, 24, 1, (0, 2), (2, 3), 30, 0),
+    # 32 observed nodes fill the first dword: clamped nodes first would add an
+    # observed dword, so select
+    (70, 250, 16, 1, (0, 2), (1, 2), 32, 0),
+    # accumulator offsets: the bias slot in the unused half of the only dword
+    # (16 nodes), an odd m-tile count (48), two k-fragments (150; 130 with an
+    # odd m-tile count and two condition groups), no clamps at all
+    (16, 50, 4, 1, (0, 2), (1, 2), 6, 1),
+    (48, 150, 10, 2, (0, 2), (1, 2), 12, 1),
+    (150, 500, 8, 1, (0, 2), (1, 2), 40, 1),
+    (130, 420, 17, 2, (0, 2), (1, 2), 12, 1),
+    (30, 90, 6, 1, (0, 2), (0, 0), 8, 1),
+])
+def test_run_clamp_hold_paths(N, E, C, d, values, clamps, O, by_offset):
+    """The stage kernel holds clamped nodes either by accumulator offsets of
+    the first two m-tiles (clamped nodes placed first) or by a select on every
+    state dword; both paths, at the layout corner cases, against the oracle."""
+    prob, _ = random_problem(400 + N + C, n_nodes=N, n_edges=E, n_cond=C, n_steps=9, n_times=3, n_obs=O,
+                             noise=0.1, clamps=clamps, step_size=d, clamp_values=values)
+    if 1 in values:
+        assert (prob["clamp"] == 1).any()
+    assert _sa().Problem(prob).info["clamps_by_offset"] == by_offset
+    x0 = synth.feasible_params(np.random.default_rng(N + C), 24, prob["row_ptr"], prob["src"])
+    _compare_runs(prob, x0, 13, T0=1.2, rho=0.7, n_stages=3, L=60)
+
+
+def test_stored_workloads_hold_clamps_by_offset():
+    for name in ("c1", "c2", "c3"):
+        assert _sa().Problem(synth.load_workload(name)).info["clamps_by_offset"] == 1, name
+
+
 def test_run_c3_truncated():
     w = synth.load_workload("c3")
     s = synth.bench_schedule("c3")
