@@ -336,20 +336,21 @@ __device__ __forceinline__ void write_states(const v4i (&B)[NK], const DevProble
 // step t-1 (B) and writes those of step t (NB).  M-tile mt's four rows are
 // nibbles 4mt .. 4mt+3 of its lane group's slots, so two m-tiles fill one
 // dword, which then takes the clamp select (mask CM: clamped nodes get their
-// old state as target, so they hold) and the step.  With RT only the first nm
-// m-tiles and nk k-fragments are present (a smaller network in a larger
-// layout).
+// old state as target, so they hold) and the step.  Only the first NMR
+// m-tiles of the NM-tile layout hold nodes (a smaller network in a larger
+// layout); dwords past them carry over.
 // HOLD: held nodes keep their state through a per-dword select with CM;
 // without HOLD, every clamped node is in the first dword, OF holds the
 // accumulator offsets of m-tiles 0 and 1 (clamped nodes forced to their
 // clamp value by the product, DevProblem::cofs) and no select is needed.
-template <int NM, int NK, int D, bool RT, bool HOLD = true>
+template <int NMR, int NM, int NK, int D, bool HOLD = true>
 __device__ __forceinline__ void time_step(const ATile<NM, NK> &A, const v4i (&B)[NK], v4i (&NB)[NK],
-                                          const v4i (&CM)[NK], int nm, int nk, const v4f *OF = nullptr) {
+                                          const v4i (&CM)[NK], const v4f *OF = nullptr) {
+  static_assert(NMR >= 1 && NMR <= NM, "active m-tiles within the layout");
   v8i bw[NK];
 #pragma unroll
   for (int kf = 0; kf < NK; ++kf) bw[kf] = widen(B[kf]);
-  constexpr int NW = (NM + 1) / 2;  // dwords holding m-tile rows
+  constexpr int NW = (NMR + 1) / 2;  // dwords holding m-tile rows
   static_for<NW>([&](auto wc) SA_INLINE {
     constexpr int w = decltype(wc)::value;
     constexpr int kf = w / 4, dw = w % 4;
@@ -357,26 +358,21 @@ __device__ __forceinline__ void time_step(const ATile<NM, NK> &A, const v4i (&B)
     static_for<2>([&](auto hc) SA_INLINE {
       constexpr int h = decltype(hc)::value;
       constexpr int mt = 2 * w + h;
-      acc[h] = v4f{0.f, 0.f, 0.f, 0.f};
-      if constexpr (!HOLD && mt < 2 && mt < NM) acc[h] = OF[mt];
-      if constexpr (mt < NM) {
-        if (!RT || mt < nm) {
-          static_for<NK>([&](auto kc) SA_INLINE {
-            constexpr int k = decltype(kc)::value;
-            if (!RT || k < nk) acc[h] = mfma_fp4(afrag<mt, k>(A), bw[k], acc[h]);
-          });
-        }
+      if constexpr (mt < NMR) {
+        acc[h] = v4f{0.f, 0.f, 0.f, 0.f};
+        if constexpr (!HOLD && mt < 2) acc[h] = OF[mt];
+        static_for<NK>([&](auto kc) SA_INLINE {
+          constexpr int k = decltype(kc)::value;
+          acc[h] = mfma_fp4(afrag<mt, k>(A), bw[k], acc[h]);
+        });
       }
     });
     // The code word is built in the register of a spent result (no copy):
-    // bytes no m-tile writes hold no node and are held by CM.
+    // bytes no m-tile writes hold no node (or the bias) and are held.
     uint32_t x = __builtin_bit_cast(uint32_t, acc[0][0]);
     static_for<2>([&](auto hc) SA_INLINE {
       constexpr int h = decltype(hc)::value;
-      constexpr int mt = 2 * w + h;
-      if constexpr (mt < NM) {
-        if (!RT || mt < nm) x = put_codes(x, acc[h], h);
-      }
+      if constexpr (2 * w + h < NMR) x = put_codes(x, acc[h], h);
     });
     const uint32_t s = (uint32_t)B[kf][dw];
     if constexpr (HOLD) {
@@ -384,8 +380,8 @@ __device__ __forceinline__ void time_step(const ATile<NM, NK> &A, const v4i (&B)
       // cm ? s : next bitwise, one v_bitop3_b32 (truth table indexed by
       // (next << 2) | (s << 1) | cm: set for 3, 4, 6, 7)
       NB[kf][dw] = (int)__builtin_amdgcn_bitop3_b32(next_states<D>(x, s), s, cm, 0xD8);
-    } else if constexpr (2 * w + 1 >= NM) {
-      // the dword's second m-tile is beyond the layout: its nibbles (the bias
+    } else if constexpr (2 * w + 1 >= NMR) {
+      // the dword's second m-tile is beyond the rows: its nibbles (the bias
       // slot when the node count is a multiple of 16, else empty slots) hold
       NB[kf][dw] = (int)__builtin_amdgcn_bitop3_b32(next_states<D>(x, s), s, 0xFFFF0000u, 0xD8);
     } else {
@@ -397,50 +393,46 @@ __device__ __forceinline__ void time_step(const ATile<NM, NK> &A, const v4i (&B)
     constexpr int q = decltype(qc)::value;
     if constexpr (q >= NW) NB[q >> 2][q & 3] = B[q >> 2][q & 3];
   });
-  if constexpr (!RT) {
-    // keep the whole step in one block and let the m-tiles' integer work run
-    // under the next m-tile's matrix products
+  // keep the whole step in one block and let the m-tiles' integer work run
+  // under the next m-tile's matrix products
 #pragma unroll
-    for (int kf = 0; kf < NK; ++kf) asm volatile("" : "+v"(NB[kf]));
-    // integer instructions per dword: 4 conversions, the update, the select
-    constexpr int kValu = (D == 1 ? 11 : 10) - (HOLD ? 0 : 1);
+  for (int kf = 0; kf < NK; ++kf) asm volatile("" : "+v"(NB[kf]));
+  // integer instructions per dword: 4 conversions, the update, the select
+  constexpr int kValu = (D == 1 ? 11 : 10) - (HOLD ? 0 : 1);
+  __builtin_amdgcn_sched_group_barrier(0x008, 2 * NK, 0);
+  static_for<NW - 1>([&](auto) SA_INLINE {
     __builtin_amdgcn_sched_group_barrier(0x008, 2 * NK, 0);
-    static_for<NW - 1>([&](auto) SA_INLINE {
-      __builtin_amdgcn_sched_group_barrier(0x008, 2 * NK, 0);
-      __builtin_amdgcn_sched_group_barrier(0x002, kValu, 0);
-    });
-    __builtin_amdgcn_sched_group_barrier(0x002, kValu + 2, 0);
-  }
+    __builtin_amdgcn_sched_group_barrier(0x002, kValu, 0);
+  });
+  __builtin_amdgcn_sched_group_barrier(0x002, kValu + 2, 0);
 }
 
-// Simulates every condition for the chain whose parameters are in A and
-// returns this lane's share of the mismatch M (§2.3).  obs_r/obs_w:
-// [CG][K][nd][64] tables.  The two state buffers alternate between steps.
-// Without a trajectory to record, the simulation ends at the last observed
-// time (later states do not enter M).
-template <int NM, int NK, int D, bool TRAJ, bool RT = false, bool HOLD = true>
-__device__ __forceinline__ int lane_mismatch(const ATile<NM, NK> &A, const DevProblem &pb, int lane,
-                                             const uint32_t *obs_r, const uint32_t *obs_w,
-                                             int8_t *__restrict__ traj) {
-  const int nm = RT ? pb.nm : NM, nk = RT ? pb.nk : NK;
+// Simulates every condition for the chain whose parameters are in A, with
+// NMR m-tiles holding nodes, and returns this lane's share of the mismatch M
+// (§2.3).  obs_r/obs_w: [CG][K][nd][64] tables.  The two state buffers
+// alternate between steps.  Without a trajectory to record, the simulation
+// ends at the last observed time (later states do not enter M).
+template <int NMR, int NM, int NK, int D, bool TRAJ, bool HOLD>
+__device__ __forceinline__ int lane_mismatch_n(const ATile<NM, NK> &A, const DevProblem &pb, int lane,
+                                               const uint32_t *obs_r, const uint32_t *obs_w,
+                                               int8_t *__restrict__ traj) {
   int total = 0;
   for (int cg = 0; cg < pb.CG; ++cg) {
     v4i B0[NK], B1[NK], CM[NK];
     v4f OF[2];
-    const int base = cg * 4 * nk;
+    const int base = cg * 4 * NK;
 #pragma unroll
     for (int kt = 0; kt < NK; ++kt)
 #pragma unroll
       for (int dw = 0; dw < 4; ++dw) {
-        const bool present = !RT || kt < nk;
         const int at = (base + kt * 4 + dw) * kWave + lane;
-        B0[kt][dw] = present ? (int)pb.b0[at] : 0;
-        if constexpr (HOLD) CM[kt][dw] = present ? (int)pb.cmask[at] : -1;
+        B0[kt][dw] = (int)pb.b0[at];
+        if constexpr (HOLD) CM[kt][dw] = (int)pb.cmask[at];
       }
     if constexpr (!HOLD) {
       const v4f *of = reinterpret_cast<const v4f *>(pb.cofs) + (size_t)cg * 2 * kWave + lane;
 #pragma unroll
-      for (int mt = 0; mt < 2 && mt < NM; ++mt) OF[mt] = of[(size_t)mt * kWave];
+      for (int mt = 0; mt < 2 && mt < NMR; ++mt) OF[mt] = of[(size_t)mt * kWave];
     }
     const int c = cg * 16 + (lane & 15);
     const uint32_t *rbase = obs_r + (size_t)cg * pb.K * pb.nd * kWave;
@@ -459,17 +451,42 @@ __device__ __forceinline__ int lane_mismatch(const ATile<NM, NK> &A, const DevPr
     const int t_end = TRAJ ? pb.T : load_uniform(pb.obs_t, pb.K - 1);
     int t = 1;
     for (; t + 1 <= t_end; t += 2) {
-      time_step<NM, NK, D, RT, HOLD>(A, B0, B1, CM, nm, nk, OF);
+      time_step<NMR, NM, NK, D, HOLD>(A, B0, B1, CM, OF);
       observe(B1, t);
-      time_step<NM, NK, D, RT, HOLD>(A, B1, B0, CM, nm, nk, OF);
+      time_step<NMR, NM, NK, D, HOLD>(A, B1, B0, CM, OF);
       observe(B0, t + 1);
     }
     if (t <= t_end) {
-      time_step<NM, NK, D, RT, HOLD>(A, B0, B1, CM, nm, nk, OF);
+      time_step<NMR, NM, NK, D, HOLD>(A, B0, B1, CM, OF);
       observe(B1, t);
     }
   }
   return total;
+}
+
+// Smallest m-tile count a layout of NM m-tiles serves at run time (the size
+// classes of the many-network kernel: 1-4, 5-8 and 9-10 m-tiles).
+constexpr int rt_min_tiles(int nm) { return nm <= 4 ? 1 : nm <= 8 ? 5 : 9; }
+
+// RT: the network may have fewer m-tiles than the layout (pb.nm, from
+// rt_min_tiles(NM) to NM; its k-fragments always equal NK): the simulation
+// runs the variant compiled for that count, so the time step holds no
+// run-time bound.
+template <int NM, int NK, int D, bool TRAJ, bool RT = false, bool HOLD = true>
+__device__ __forceinline__ int lane_mismatch(const ATile<NM, NK> &A, const DevProblem &pb, int lane,
+                                             const uint32_t *obs_r, const uint32_t *obs_w,
+                                             int8_t *__restrict__ traj) {
+  if constexpr (!RT) {
+    return lane_mismatch_n<NM, NM, NK, D, TRAJ, HOLD>(A, pb, lane, obs_r, obs_w, traj);
+  } else {
+    int total = 0;
+    const int nm = pb.nm;
+    static_for<NM - rt_min_tiles(NM) + 1>([&](auto ic) SA_INLINE {
+      constexpr int NMR = rt_min_tiles(NM) + decltype(ic)::value;
+      if (nm == NMR) total = lane_mismatch_n<NMR, NM, NK, D, TRAJ, HOLD>(A, pb, lane, obs_r, obs_w, traj);
+    });
+    return total;
+  }
 }
 
 // §2.5.3: this lane's share of V = #(no non-zero out-edge) + #(no +1 in-edge).

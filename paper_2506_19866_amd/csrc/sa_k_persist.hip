@@ -146,7 +146,12 @@ size_t persistent_smem_bytes(const DevProblem &pb, int waves) {
 // size classes: (m-tiles, k-tiles) of the layout each class runs in
 #define SA_PERSISTENT_CLASSES(X) X(0, 4, 1) X(1, 8, 1) X(2, 10, 2)
 
+// The class of a network with nm m-tiles; every network of a class has the
+// class's k-fragments, and its m-tile count lies between rt_min_tiles of the
+// class layout and the layout's own, which the time-step variants cover.
 int persistent_class(int nm) { return nm <= 4 ? 0 : nm <= 8 ? 1 : 2; }
+static_assert(rt_min_tiles(4) == 1 && rt_min_tiles(8) == 5 && rt_min_tiles(10) == 9,
+              "size classes and time-step variants agree");
 
 int persistent_blocks_per_cu(int cls, int waves, size_t smem) {
   int blocks = 0;

@@ -106,13 +106,13 @@ __device__ __forceinline__ int refresh_simulation(const ATile<NM, NK> &A, const 
     const int t_end = load_uniform(pb.obs_t, pb.K - 1);  // later states enter no aggregate
     int t = 1;
     for (; t + 1 <= t_end; t += 2) {
-      time_step<NM, NK, D, false>(A, B0, B1, CM, NM, NK);
+      time_step<NM, NM, NK, D>(A, B0, B1, CM);
       observe(B1, t);
-      time_step<NM, NK, D, false>(A, B1, B0, CM, NM, NK);
+      time_step<NM, NM, NK, D>(A, B1, B0, CM);
       observe(B0, t + 1);
     }
     if (t <= t_end) {
-      time_step<NM, NK, D, false>(A, B0, B1, CM, NM, NK);
+      time_step<NM, NM, NK, D>(A, B0, B1, CM);
       observe(B1, t);
     }
     // byte b of a parity-p accumulator holds nibble 2b + p: slot 8*q4 + 2b + p
