@@ -470,8 +470,9 @@ constexpr int rt_min_tiles(int nm) { return nm <= 4 ? 1 : nm <= 8 ? 5 : 9; }
 
 // RT: the network may have fewer m-tiles than the layout (pb.nm, from
 // rt_min_tiles(NM) to NM; its k-fragments always equal NK): the simulation
-// runs the variant compiled for that count, so the time step holds no
-// run-time bound.
+// runs the variant compiled for that count and for the network's way of
+// holding clamped nodes (pb.hold_by_offset; HOLD is then unused), so the
+// time step holds no run-time bound.
 template <int NM, int NK, int D, bool TRAJ, bool RT = false, bool HOLD = true>
 __device__ __forceinline__ int lane_mismatch(const ATile<NM, NK> &A, const DevProblem &pb, int lane,
                                              const uint32_t *obs_r, const uint32_t *obs_w,
@@ -481,9 +482,15 @@ __device__ __forceinline__ int lane_mismatch(const ATile<NM, NK> &A, const DevPr
   } else {
     int total = 0;
     const int nm = pb.nm;
+    const bool by_offset = pb.hold_by_offset != 0;
     static_for<NM - rt_min_tiles(NM) + 1>([&](auto ic) SA_INLINE {
       constexpr int NMR = rt_min_tiles(NM) + decltype(ic)::value;
-      if (nm == NMR) total = lane_mismatch_n<NMR, NM, NK, D, TRAJ, HOLD>(A, pb, lane, obs_r, obs_w, traj);
+      if (nm == NMR) {
+        if (by_offset)
+          total = lane_mismatch_n<NMR, NM, NK, D, TRAJ, false>(A, pb, lane, obs_r, obs_w, traj);
+        else
+          total = lane_mismatch_n<NMR, NM, NK, D, TRAJ, true>(A, pb, lane, obs_r, obs_w, traj);
+      }
     });
     return total;
   }

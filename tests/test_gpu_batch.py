@@ -100,6 +100,36 @@ def test_uneven_batch_island_restart():
     _check_against_oracle(run, probs, x0s, seed, 2.0, 0.8, S, L, group_size=3)
 
 
+# (nodes, edges, conditions, clamp values, observed nodes): every m-tile count
+# of the three size classes, the bias slot in each position it can take
+# (inside a computed m-tile, in the unused half of the last dword, past the
+# rows), and both ways of holding clamped nodes (a clamp value of 1, or
+# clamped and observed nodes that do not fit the first dword, take the select)
+_LAYOUT_CASES = [(16, 50, 5, (0, 2), 3), (26, 80, 6, (0, 2), 4), (33, 90, 7, (1, 2), 5), (48, 140, 9, (0, 2), 8),
+                 (64, 200, 12, (0, 2), 10), (80, 240, 6, (0, 1, 2), 13), (96, 290, 8, (0, 2), 16),
+                 (112, 330, 16, (0, 2), 18), (120, 360, 5, (0, 2), 20), (128, 380, 4, (0, 2), 21),
+                 (144, 420, 8, (1,), 24), (144, 420, 6, (0, 2), 24), (150, 450, 10, (0, 2), 18)]
+
+
+def test_batch_every_tile_count_and_clamp_form():
+    """One persistent run over networks of every m-tile count the size classes
+    serve, mixing the accumulator-offset and select forms of clamping, each
+    network bit-exact against the oracle."""
+    from tests.problems import random_problem
+    sa = _sa()
+    probs = [random_problem(700 + N + C, n_nodes=N, n_edges=E, n_cond=C, n_steps=8, n_times=3, n_obs=O,
+                            noise=0.1, clamps=(1, 2), clamp_values=v)[0] for N, E, C, v, O in _LAYOUT_CASES]
+    P = [sa.Problem(p) for p in probs]
+    forms = [q.info["clamps_by_offset"] for q in P]
+    assert forms == [1, 1, 0, 1, 1, 0, 1, 0, 1, 1, 0, 1, 1]
+    n = 9
+    x0s = [synth.feasible_params(np.random.default_rng(50 + i), n, p["row_ptr"], p["src"]) for i, p in enumerate(probs)]
+    S, L, seed = 3, 40, 23
+    run = sa.Run(P, [_dev(x) for x in x0s], seed=seed, T0=2.0, rho=0.8, n_stages=S, steps_per_stage=L,
+                 use_graph=True, chains_per_block=0)
+    _check_against_oracle(run, probs, x0s, seed, 2.0, 0.8, S, L)
+
+
 def test_batch_independent_of_tiling_and_launch_split():
     """Results do not depend on the chains per workgroup or on how the stages
     are split into launch calls, and equal the oracle's per network."""
