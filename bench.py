@@ -43,6 +43,11 @@ sys.path.insert(0, ROOT)
 CU, CLOCK_HZ = 256, 2.4e9
 ALU_PEAK_OPS = CU * 64 * CLOCK_HZ
 FP4_DENSE_PEAK_FLOPS = 10.1e15
+HBM_PEAK_BYTES = 8.0e12
+# LDS: 256 CUs x 256 bytes per clock x 2.4 GHz; the measured 16-byte read
+# rate of sa_measure_peak (reported beside it) is 96% of that, more than 128
+# bytes per clock could deliver
+LDS_PEAK_BYTES = CU * 256 * CLOCK_HZ
 PROFILES = os.path.join(ROOT, "profiles")
 STAGE_KERNEL_SOURCES = ("paper_2506_19866_amd/csrc/sa_k_stage.hip", "paper_2506_19866_amd/csrc/sa_chain.h",
                         "paper_2506_19866_amd/csrc/sa_device.h", "paper_2506_19866_amd/csrc/sa_internal.h")
@@ -102,11 +107,12 @@ def measured_peaks() -> dict:
     """Device-wide rates of the instructions the kernels are bound by
     (sa_measure_peak): 32-bit lane-ops/s of v_xor / v_add / v_bitop3, values
     per second of the fp4 (2 per instruction) and fp6 (32 per instruction)
-    packing conversions, flops/s of the fp4 x fp4 and fp4 x fp6 products."""
+    packing conversions, flops/s of the fp4 x fp4 and fp4 x fp6 products,
+    bytes/s of 16-byte LDS reads."""
     from paper_2506_19866_amd import sa
     kinds = {"valu_xor": sa.SA_PEAK_VALU_XOR, "valu_add": sa.SA_PEAK_VALU_ADD, "valu_bitop3": sa.SA_PEAK_VALU_BITOP3,
              "cvt_fp4": sa.SA_PEAK_CVT_FP4, "mfma_fp4": sa.SA_PEAK_MFMA_FP4, "cvt_fp6": sa.SA_PEAK_CVT_FP6,
-             "mfma_fp4_fp6": sa.SA_PEAK_MFMA_FP4_FP6}
+             "mfma_fp4_fp6": sa.SA_PEAK_MFMA_FP4_FP6, "lds_read": sa.SA_PEAK_LDS_READ}
     out = {k: sa.measure_peak(v)[0] for k, v in kinds.items()}
     out["valu"] = max(out["valu_xor"], out["valu_add"], out["valu_bitop3"])
     return out
@@ -128,12 +134,13 @@ def counters_from_profiles(launch_key: str, kind: str = "stage"):
 
 
 def alu_roofline(ops_per_launch: float, avg_launch_s: float, peaks: dict | None, kernel: str, traffic,
-                 counters=None, macs_per_launch: float | None = None, dense_macs_per_launch: float | None = None
-                 ) -> dict:
+                 counters=None, macs_per_launch: float | None = None, dense_macs_per_launch: float | None = None,
+                 lds_bytes_per_launch: float | None = None, lds_what: str = "") -> dict:
     """The roofline object: algorithmic integer ALU work against the derived
     ALU peak (and the measured one), plus the matrix-core part of the work
-    against the dense fp4 peak and, from committed counters, the VALU
-    instructions the kernel actually issued."""
+    against the dense fp4 peak, the HBM and LDS bandwidth the launch used,
+    and, from committed counters, the VALU instructions the kernel actually
+    issued."""
     achieved = ops_per_launch / avg_launch_s
     r = {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK_OPS / 1e12, "unit": "TOP/s",
          "frac": achieved / ALU_PEAK_OPS, "traffic": traffic, "kernel": kernel,
@@ -152,6 +159,18 @@ def alu_roofline(ops_per_launch: float, avg_launch_s: float, peaks: dict | None,
         if peaks:
             m["peak_measured"] = peaks["mfma_fp4"] / 1e12
         r["mfma"] = m
+    if traffic:
+        r["hbm"] = {"achieved": traffic / avg_launch_s / 1e9, "peak": HBM_PEAK_BYTES / 1e9, "unit": "GB/s",
+                    "frac": traffic / avg_launch_s / HBM_PEAK_BYTES,
+                    "what": "copy-calibrated FETCH_SIZE + WRITE_SIZE bytes per launch (traffic) / its duration"}
+    if lds_bytes_per_launch is not None:
+        lds = {"achieved": lds_bytes_per_launch / avg_launch_s / 1e9, "peak": LDS_PEAK_BYTES / 1e9, "unit": "GB/s",
+               "frac": lds_bytes_per_launch / avg_launch_s / LDS_PEAK_BYTES, "what": lds_what,
+               "peak_note": "256 CUs x 256 bytes per clock x 2.4 GHz"}
+        if peaks and peaks.get("lds_read"):
+            lds["peak_measured"] = peaks["lds_read"] / 1e9
+            lds["frac_measured"] = lds_bytes_per_launch / avg_launch_s / peaks["lds_read"]
+        r["lds"] = lds
     if counters:
         issued = counters["sq_insts_valu_per_launch"] * 64 / (counters["avg_launch_ms"] * 1e-3)
         r["valu_issued"] = {"lane_ops_per_s": issued / 1e12, "unit": "TOP/s",
@@ -561,7 +580,8 @@ def main() -> int:
     from paper_2506_19866_amd import sa, synth
     if args.mode == "peaks":
         peaks = measured_peaks()
-        print(json.dumps({"mode": "peaks", "unit": "lane-ops/s (valu_*), values/s (cvt_*), flop/s (mfma_*)",
+        print(json.dumps({"mode": "peaks",
+                          "unit": "lane-ops/s (valu_*), values/s (cvt_*), flop/s (mfma_*), bytes/s (lds_read)",
                           "derived_alu_peak": ALU_PEAK_OPS, "published_fp4_dense_peak": FP4_DENSE_PEAK_FLOPS,
                           **peaks}), flush=True)
         return 0
@@ -640,7 +660,26 @@ def main() -> int:
         t_last = int(np.max(prob["obs_t"]))
         cols = -(-prob["n_cond"] // 16) * 16
         dense = sims_mean * cols * t_last * 16 * info["tiles_m"] * 128 * info["frags_k"]
-    roofline = alu_roofline(ops_per_launch, avg_launch_s, peaks, kernel, traffic, counters, macs, dense)
+    sims_mean = float(np.mean(sims))
+    if priority:
+        # every simulated step reads one observation dword per lane, and each
+        # node-lane fetches its regulators' states by one lane permute per
+        # regulator slot (LDS-pipe traffic, 4 bytes per lane)
+        steps = prob["n_cond"] * (prob["n_steps"] + 1)
+        lc = 16 if prob["n_nodes"] <= 16 else 32 if prob["n_nodes"] <= 32 else 64
+        max_in = int(np.diff(prob["row_ptr"]).max())
+        slots = 0 if lc <= 32 else 8 if max_in <= 8 else 16 if max_in <= 16 else 0
+        per_sim = steps * lc * 4 + prob["n_cond"] * prob["n_steps"] * lc * slots * 4
+        lds_what = ("per simulation C*(T+1)*LC observation dwords + C*T*LC*slots lane-permute dwords, 4 bytes each "
+                    "(the permutes are the kernel's own gathers, not algorithmic reads)")
+    else:
+        # the scoring reads, at every observed time, the reference and weight
+        # dwords of the lane's observed slots from LDS
+        cg = -(-prob["n_cond"] // 16)
+        per_sim = len(prob["obs_t"]) * P.info["obs_dwords"] * 2 * 4 * 64 * cg
+        lds_what = "per simulation K x (scored dwords) x 2 tables x 4 bytes x 64 lanes x condition groups"
+    roofline = alu_roofline(ops_per_launch, avg_launch_s, peaks, kernel, traffic, counters, macs, dense,
+                            sims_mean * per_sim, lds_what)
     roofline["simulations_per_launch"] = float(np.mean(sims))
     roofline["candidates_per_launch"] = float(n * L)
     out = {

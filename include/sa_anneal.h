@@ -116,6 +116,9 @@ typedef struct {
   int32_t clamps_by_offset; /* 1: the stage kernel holds clamped nodes through accumulator offsets of
                                the product (every clamp value 0 or 2 and at most 32 clamped nodes,
                                placed in the first state dword); 0: through a select per dword */
+  int32_t obs_dwords;       /* synchronous model: packed state dwords per lane that the scoring reads
+                               (with their reference and weight dwords) at every observed time; 0 for
+                               the priority model */
 } sa_problem_info;
 
 /* Validates the description, precomputes the weights W and lambda and the
@@ -388,13 +391,16 @@ int sa_mlp_train_step(sa_mlp *model, const uint16_t *x_dev, const float *y_dev, 
  *     flops per second (2 x 16 x 16 x 128 per instruction);
  *   SA_PEAK_CVT_FP6: v_cvt_scalef32_2xpk16_fp6_f32 (32 floats to 32 fp6
  *     codes per lane), in values converted per second;
- *   SA_PEAK_MFMA_FP4_FP6: the same product with the B operand read as fp6.
- * (The last two price an fp6 state encoding against the fp4 one.)
+ *   SA_PEAK_MFMA_FP4_FP6: the same product with the B operand read as fp6;
+ *   SA_PEAK_LDS_READ: 16-byte LDS reads (ds_read_b128), every lane of a wave
+ *     reading consecutive words (no bank conflict), in bytes per second.
+ * (SA_PEAK_CVT_FP6 and SA_PEAK_MFMA_FP4_FP6 price an fp6 state encoding
+ * against the fp4 one.)
  * rate (host) receives the rate; ms (host, nullable) the best of two timed
  * launches after a warm-up one.  Allocates a small buffer, synchronises
  * `stream`. */
 enum { SA_PEAK_VALU_XOR = 0, SA_PEAK_VALU_ADD = 1, SA_PEAK_VALU_BITOP3 = 2, SA_PEAK_CVT_FP4 = 3,
-       SA_PEAK_MFMA_FP4 = 4, SA_PEAK_CVT_FP6 = 5, SA_PEAK_MFMA_FP4_FP6 = 6 };
+       SA_PEAK_MFMA_FP4 = 4, SA_PEAK_CVT_FP6 = 5, SA_PEAK_MFMA_FP4_FP6 = 6, SA_PEAK_LDS_READ = 7 };
 int sa_measure_peak(int32_t kind, double *rate, double *ms, void *stream);
 
 /* Message of the last failure on the calling thread ("" if none). */

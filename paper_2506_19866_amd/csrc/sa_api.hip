@@ -264,6 +264,7 @@ static int create_priority(const sa_problem_desc *d, const std::vector<int> &W, 
   in.penalty = (int32_t)lambda;
   in.max_cost = (int32_t)max_cost;
   in.clamps_by_offset = 0;
+  in.obs_dwords = 0;
   *out = pr;
   return SA_OK;
 }
@@ -547,6 +548,7 @@ extern "C" int sa_create_problem(const sa_problem_desc *d, sa_problem **out) {
   in.penalty = (int32_t)lambda;
   in.max_cost = (int32_t)max_cost;
   in.clamps_by_offset = hold_by_offset ? 1 : 0;
+  in.obs_dwords = nd;
   *out = pr;
   return SA_OK;
 }
@@ -1442,7 +1444,7 @@ extern "C" int sa_run_chains_noalloc(const sa_problem *prob, const sa_run_desc *
 // ---------------------------------------------------------------------------
 extern "C" int sa_measure_peak(int32_t kind, double *rate, double *ms_out, void *stream) {
   if (!rate) return fail(SA_ERR_ARG, "rate is NULL");
-  if (kind < SA_PEAK_VALU_XOR || kind > SA_PEAK_MFMA_FP4_FP6) return fail(SA_ERR_ARG, "unknown peak kind %d", kind);
+  if (kind < SA_PEAK_VALU_XOR || kind > SA_PEAK_LDS_READ) return fail(SA_ERR_ARG, "unknown peak kind %d", kind);
   hipStream_t s = (hipStream_t)stream;
   int dev = 0, cus = 0;
   SA_HIP(hipGetDevice(&dev), "hipGetDevice");

@@ -104,6 +104,45 @@ __global__ __launch_bounds__(256) void probe_mfma_kernel(float *sink, int iters,
   if (x == never) sink[blockIdx.x * blockDim.x + threadIdx.x] = x;
 }
 
+// LDS read bandwidth: the block fills 16 KB of LDS, then every lane reads
+// 16-byte words, the 64 lanes of a wave consecutive ones (every bank once
+// per quarter of the wave), into 8 independent accumulators; the base index
+// alternates between loop trips and is opaque to the compiler, so no read
+// can be hoisted or merged (every index stays below 1024).
+constexpr int kLdsWords = 1024;  // 16-byte words
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void probe_lds_kernel(uint32_t *sink, int iters, uint32_t never) {
+  __shared__ v4u buf[kLdsWords];
+  for (int i = threadIdx.x; i < kLdsWords; i += blockDim.x)
+    buf[i] = v4u{(uint32_t)i, (uint32_t)i * 3u, (uint32_t)i * 5u, (uint32_t)i * 7u};
+  __syncthreads();
+  uint32_t acc[kProbeChains];
+#pragma unroll
+  for (int j = 0; j < kProbeChains; ++j) acc[j] = 0;
+  const int lane_word = (int)threadIdx.x & 63;
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int r = 0; r < kProbeUnroll; ++r) {
+      // 8 reads in flight per wave, from one opaque base and immediate offsets
+      int base = lane_word + 512 * ((i + r) & 1);
+      asm volatile("" : "+v"(base));
+      v4u v[kProbeChains];
+#pragma unroll
+      for (int j = 0; j < kProbeChains; ++j) v[j] = buf[base + 64 * j];
+#pragma unroll
+      for (int j = 0; j < kProbeChains; ++j) {
+        asm volatile("" : : "v"(v[j]));  // all 16 bytes are read
+        acc[j] ^= v[j].x;
+        asm volatile("" : "+v"(acc[j]));
+      }
+    }
+  }
+  uint32_t x = 0;
+#pragma unroll
+  for (int j = 0; j < kProbeChains; ++j) x ^= acc[j];
+  if (x == never) sink[blockIdx.x * blockDim.x + threadIdx.x] = x;
+}
+
 }  // namespace
 
 int probe_iters(int kind) {
@@ -115,18 +154,21 @@ int probe_iters(int kind) {
       return 2048;
     case SA_PEAK_CVT_FP6:
       return 256;
+    case SA_PEAK_LDS_READ:
+      return 1024;
     default:
       return 8192;
   }
 }
 
 // Work of one launch: lane-ops (VALU), values converted (conversions), flops
-// (matrix products).
+// (matrix products), bytes (LDS reads).
 double probe_work(int kind, int blocks, int threads) {
   const double waves = (double)blocks * (threads / 64);
   if (kind == SA_PEAK_CVT_FP6) return waves * probe_iters(kind) * 8 * 64 * 32.0;
   const double instr = waves * probe_iters(kind) * kProbeUnroll * kProbeChains;
   if (kind == SA_PEAK_MFMA_FP4 || kind == SA_PEAK_MFMA_FP4_FP6) return instr * 2.0 * 16 * 16 * 128;
+  if (kind == SA_PEAK_LDS_READ) return instr * 64.0 * 16.0;
   return instr * 64.0 * (kind == SA_PEAK_CVT_FP4 ? 2.0 : 1.0);
 }
 
@@ -156,6 +198,9 @@ int launch_probe(int kind, void *sink, int blocks, int threads, void *stream) {
       break;
     case SA_PEAK_MFMA_FP4_FP6:
       probe_mfma_kernel<true><<<blocks, threads, 0, s>>>(static_cast<float *>(sink), iters, -1.0e30f);
+      break;
+    case SA_PEAK_LDS_READ:
+      probe_lds_kernel<<<blocks, threads, 0, s>>>(u, iters, never);
       break;
     default:
       return (int)hipErrorInvalidValue;

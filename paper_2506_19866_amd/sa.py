@@ -33,7 +33,7 @@ EXPORTS = ("sa_create_problem", "sa_destroy_problem", "sa_problem_get_info", "sa
            "sa_mlp_destroy", "sa_mlp_get_params", "sa_mlp_set_params", "sa_mlp_forward", "sa_mlp_gradients",
            "sa_mlp_train_step", "sa_measure_peak", "sa_last_error")
 SA_PEAK_VALU_XOR, SA_PEAK_VALU_ADD, SA_PEAK_VALU_BITOP3, SA_PEAK_CVT_FP4, SA_PEAK_MFMA_FP4 = 0, 1, 2, 3, 4
-SA_PEAK_CVT_FP6, SA_PEAK_MFMA_FP4_FP6 = 5, 6
+SA_PEAK_CVT_FP6, SA_PEAK_MFMA_FP4_FP6, SA_PEAK_LDS_READ = 5, 6, 7
 MLP_INPUTS, MLP_HIDDEN = 32, 256
 MLP_N_PARAMS = MLP_INPUTS * MLP_HIDDEN + MLP_HIDDEN + 1
 
@@ -61,7 +61,7 @@ class _ProblemDesc(C.Structure):
 class _ProblemInfo(C.Structure):
     _fields_ = [(k, C.c_int32) for k in (
         "n_params", "n_nodes", "n_edges", "n_conditions", "n_steps", "n_obs_times", "n_obs_nodes",
-        "weight_sum", "penalty", "max_cost", "clamps_by_offset")]
+        "weight_sum", "penalty", "max_cost", "clamps_by_offset", "obs_dwords")]
 
 
 class _RunDesc(C.Structure):
