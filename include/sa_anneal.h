@@ -113,7 +113,7 @@ typedef struct {
   int32_t weight_sum; /* sum of W over all observations */
   int32_t penalty;    /* lambda in effect */
   int32_t max_cost;   /* 2 * weight_sum + lambda * 2N */
-  int32_t clamps_by_offset; /* 1: the stage kernel holds clamped nodes through accumulator offsets of
+  int32_t clamps_by_offset; /* 1: the plain kernels hold clamped nodes through accumulator offsets of
                                the product (every clamp value 0 or 2 and at most 32 clamped nodes,
                                placed in the first state dword); 0: through a select per dword */
   int32_t obs_dwords;       /* synchronous model: packed state dwords per lane that the scoring reads

@@ -307,9 +307,9 @@ extern "C" int sa_create_problem(const sa_problem_desc *d, sa_problem **out) {
   // every lane), round-robin over the four lane groups; bias after the nodes.
   // Clamped nodes go before them when that puts every clamped node in the
   // first dword of every lane without lengthening the observed dwords and
-  // every clamp value is 0 or 2: the stage kernel then holds them by
-  // accumulator offsets of the first two m-tiles (DevProblem::cofs) and
-  // needs no per-dword select.
+  // every clamp value is 0 or 2: the plain kernels (specialised and
+  // many-network) then hold them by accumulator offsets of the first two
+  // m-tiles (DevProblem::cofs) and need no per-dword select.
   std::vector<int> order, obs_index(N, -1);
   for (int o = 0; o < O; ++o) obs_index[d->obs_nodes[o]] = o;
   std::vector<char> clamped(N, 0);
