@@ -271,22 +271,25 @@ __device__ __forceinline__ uint32_t put_codes(uint32_t word, const v4f &acc, int
 // Next states of 8 nodes from the codes w of x = 2(h - 1) and the states s.
 // d = 1 moves one level towards t = clamp(h, 0, 2):
 //     [s' >= 1] = [t >= 1] or [s >= 2],   [s' >= 2] = [t >= 2] and [s >= 1];
-// d >= 2 reaches t: s' = t.  Both thresholds are formed at bit 2 of every
-// nibble, where w holds [x != 0], w >> 1 the sign of x, s [s >= 1] and
-// s << 1 [s >= 2]; [s' >= 2] then moves down to bit 1.  v_bitop3_b32 truth
+// d >= 2 reaches t: s' = t.  Both thresholds are formed at bit 1 of every
+// nibble, where w >> 2 holds [x < 0], w itself [x != 0], s [s >= 2] and
+// s >> 1 [s >= 1], each masked to that bit; one shift-or then moves
+// [s' >= 1] up to bit 2 and merges the two (v_lshl_or_b32).  Five integer
+// instructions per 8 nodes for d = 1, four for d >= 2.  v_bitop3_b32 truth
 // tables are indexed by (a << 2) | (b << 1) | c.
+constexpr uint32_t kBit1 = 0x22222222u;  // bit 1 of every nibble
 template <int D>
 __device__ __forceinline__ uint32_t next_states(uint32_t w, uint32_t s) {
-  const uint32_t u = w >> 1;
+  const uint32_t n = w >> 2;
+  uint32_t ge1, ge2;
   if constexpr (D == 1) {
-    const uint32_t ge1 = __builtin_amdgcn_bitop3_b32(u, w, s << 1, 0xBF);  // !(u & w) | c
-    const uint32_t ge2 = __builtin_amdgcn_bitop3_b32(w, u, s, 0x20);       // a & !b & c: bit 2 only
-    return __builtin_amdgcn_bitop3_b32(ge1, kBit2, ge2 >> 1, 0xEA);         // (a & b) | c
+    ge1 = __builtin_amdgcn_bitop3_b32(n, s, kBit1, 0x8A);       // (!a | b) & c
+    ge2 = __builtin_amdgcn_bitop3_b32(n, w, s >> 1, 0x08);      // !a & b & c: bit 1 only
   } else {
-    const uint32_t ge1 = __builtin_amdgcn_bitop3_b32(u, w, kBit2, 0x2A);   // !(a & b) & c
-    const uint32_t ge2 = __builtin_amdgcn_bitop3_b32(w, u, kBit2, 0x20);   // a & !b & c
-    return ge1 | (ge2 >> 1);
+    ge1 = __builtin_amdgcn_bitop3_b32(n, kBit1, 0u, 0x0C);      // !a & b
+    ge2 = __builtin_amdgcn_bitop3_b32(n, w, kBit1, 0x08);       // !a & b & c
   }
+  return (ge1 << 1) | ge2;
 }
 
 // Weighted Manhattan distance of the packed states against the reference:
@@ -398,7 +401,7 @@ __device__ __forceinline__ void time_step(const ATile<NM, NK> &A, const v4i (&B)
 #pragma unroll
   for (int kf = 0; kf < NK; ++kf) asm volatile("" : "+v"(NB[kf]));
   // integer instructions per dword: 4 conversions, the update, the select
-  constexpr int kValu = (D == 1 ? 11 : 10) - (HOLD ? 0 : 1);
+  constexpr int kValu = (D == 1 ? 10 : 9) - (HOLD ? 0 : 1);
   __builtin_amdgcn_sched_group_barrier(0x008, 2 * NK, 0);
   static_for<NW - 1>([&](auto) SA_INLINE {
     __builtin_amdgcn_sched_group_barrier(0x008, 2 * NK, 0);
