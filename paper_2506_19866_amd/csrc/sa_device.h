@@ -252,10 +252,11 @@ __device__ __forceinline__ v4f mfma_fp4(v8i a, v8i b, v4f acc) {
 
 // Writes the fp4 codes of 8x for an m-tile's four results x = 2(h - 1) into
 // bytes 2h and 2h+1 of `word` (h = m-tile parity).  The conversion saturates
-// at 6, so every code is 0x0 (x = 0), 0x7 (x >= 2) or 0xf (x <= -2) (0x8 if a
-// zero ever carried a sign): bit 3 = [x < 0], bit 2 = [x != 0].  With
-// t = clamp(h, 0, 2) (§2.1, §2.2): [t >= 2] = bit 2 and not bit 3,
-// [t >= 1] = not (bit 2 and bit 3).
+// at 6, so every code is 0x0 (x = 0), 0x7 (x >= 2) or 0xf (x <= -2): bit 3 =
+// [x < 0], bits 0-2 = [x != 0].  A zero result is +0 (the accumulators start
+// from +0 or from a non-zero offset, and exact cancellation rounds to +0), so
+// the code 0x8 of a signed zero does not occur.  With t = clamp(h, 0, 2)
+// (§2.1, §2.2): [t >= 2] = bit 2 and not bit 3, [t >= 1] = not bit 3.
 __device__ __forceinline__ uint32_t put_codes(uint32_t word, const v4f &acc, int h) {
   constexpr float kSaturate = 0.125f;  // the conversion divides by it
   if (h == 0) {
