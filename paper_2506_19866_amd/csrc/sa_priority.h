@@ -25,6 +25,8 @@
 // v_permlane32_swap).  Two more masks per node (sources with w != 0, and
 // whether an in-edge has p = +1 and w != 0) give the constraint count.
 #pragma once
+#include <climits>
+
 #include "sa_device.h"
 
 namespace sa {
@@ -54,42 +56,47 @@ __device__ __forceinline__ SegMask<LC> seg_ballot(bool pred, int base) {
 
 // Maximum / sum / or over the LC lanes of the segment, in every lane of it:
 // quad_perm swaps (lanes 1,0,3,2 and 2,3,0,1) and row rotations by 4 and 8
-// reduce each row of 16 lanes; the row swap pairs rows 0-1 and 2-3 and the
-// half-wave swap pairs the two halves.
+// reduce each row of 16 lanes.  A 32-lane segment then pairs rows 0-1 and
+// 2-3 by the row swap.  A whole wave instead lets rows 1 and 3 take the last
+// lane of the row before (row_bcast:15) and rows 2 and 3 lane 31
+// (row_bcast:31), each fused into the operation, so that lane 63 holds the
+// result, read into a scalar; `id` is the operation's identity, the value
+// lanes of the rows a broadcast leaves out combine with.
 template <int LC, typename Op>
-__device__ __forceinline__ int seg_reduce(int v, Op op) {
+__device__ __forceinline__ int seg_reduce(int v, Op op, int id) {
   v = op(v, __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xf, 0xf, false));   // quad_perm [1,0,3,2]
   v = op(v, __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xf, 0xf, false));   // quad_perm [2,3,0,1]
   v = op(v, __builtin_amdgcn_update_dpp(0, v, 0x124, 0xf, 0xf, false));  // row_ror:4
   v = op(v, __builtin_amdgcn_update_dpp(0, v, 0x128, 0xf, 0xf, false));  // row_ror:8
-  if constexpr (LC >= 32) {
+  if constexpr (LC == 32) {
     const auto r = __builtin_amdgcn_permlane16_swap((unsigned)v, (unsigned)v, false, false);
     v = op((int)r[0], (int)r[1]);
   }
   if constexpr (LC == 64) {
-    const auto r = __builtin_amdgcn_permlane32_swap((unsigned)v, (unsigned)v, false, false);
-    v = op((int)r[0], (int)r[1]);
+    v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x142, 0xa, 0xf, false));  // row_bcast:15, rows 1 and 3
+    v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x143, 0xc, 0xf, false));  // row_bcast:31, rows 2 and 3
+    v = __builtin_amdgcn_readlane(v, 63);
   }
   return v;
 }
 
 template <int LC>
 __device__ __forceinline__ int seg_max(int v) {
-  return seg_reduce<LC>(v, [](int a, int b) { return a > b ? a : b; });
+  return seg_reduce<LC>(v, [](int a, int b) { return a > b ? a : b; }, INT_MIN);
 }
 template <int LC>
 __device__ __forceinline__ int seg_sum(int v) {
-  return seg_reduce<LC>(v, [](int a, int b) { return a + b; });
+  return seg_reduce<LC>(v, [](int a, int b) { return a + b; }, 0);
 }
 template <int LC>
 __device__ __forceinline__ SegMask<LC> seg_or(SegMask<LC> v) {
   auto orr = [](int a, int b) { return a | b; };
   if constexpr (LC == 64) {
-    const uint32_t lo = (uint32_t)seg_reduce<LC>((int)(uint32_t)v, orr);
-    const uint32_t hi = (uint32_t)seg_reduce<LC>((int)(uint32_t)(v >> 32), orr);
+    const uint32_t lo = (uint32_t)seg_reduce<LC>((int)(uint32_t)v, orr, 0);
+    const uint32_t hi = (uint32_t)seg_reduce<LC>((int)(uint32_t)(v >> 32), orr, 0);
     return (uint64_t)hi << 32 | lo;
   } else {
-    return (uint32_t)seg_reduce<LC>((int)v, orr);
+    return (uint32_t)seg_reduce<LC>((int)v, orr, 0);
   }
 }
 
