@@ -195,6 +195,14 @@ __device__ __forceinline__ int pr_violations(const DevProblem &pb, int li, const
   return seg_sum<LC>(v);
 }
 
+// Median of three integers, min(max(a, lo), hi) for lo <= hi, in one
+// v_med3_i32 (the compiler forms it only for constant bounds).
+__device__ __forceinline__ int med3(int a, int lo, int hi) {
+  int r;
+  asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(lo), "v"(hi));
+  return r;
+}
+
 // One-hot byte code of a state: byte s of the dword is 1.
 __device__ __forceinline__ int pr_onehot(int s) { return 1 << (s << 3); }
 
@@ -206,14 +214,11 @@ template <int LC, int DMAX>
 __device__ __forceinline__ int pr_image(const PrNode<LC, DMAX> &nd, const PrAddr<DMAX> &ad, int s, int oh,
                                         int base) {
   if constexpr (DMAX > 0) {
-    int img0 = 0, img1 = 0;
+    int img = 0;
 #pragma unroll
-    for (int k = 0; k < DMAX; k += 2) {
-      img0 = __builtin_amdgcn_sdot4((int)nd.tab[k], __builtin_amdgcn_ds_bpermute(ad.addr[k], oh), img0, false);
-      img1 = __builtin_amdgcn_sdot4((int)nd.tab[k + 1], __builtin_amdgcn_ds_bpermute(ad.addr[k + 1], oh), img1,
-                                    false);
-    }
-    return img0 + img1;
+    for (int k = 0; k < DMAX; ++k)
+      img = __builtin_amdgcn_sdot4((int)nd.tab[k], __builtin_amdgcn_ds_bpermute(ad.addr[k], oh), img, false);
+    return img;
   } else {
     const SegMask<LC> g1 = seg_ballot<LC>(s >= 1, base), g2 = seg_ballot<LC>(s >= 2, base);
     return pr_popc<LC>(g1 & nd.a1p) + pr_popc<LC>(g1 & nd.a2p) + pr_popc<LC>(g2 & nd.b1p) +
@@ -279,9 +284,21 @@ __device__ __forceinline__ int pr_mismatch(const DevProblem &pb, int li, int bas
       const int best = seg_max<LC>(prio);
       told_any |= told;
       ready_any |= prio > 0;
-      if (prio > 0 && prio == best) {
+      // the node of the step's highest priority moves towards the goal by at
+      // most d (d >= 1).  One chain per wave: a branch around one median
+      // (|goal - s| = 2 for states in {0, 1, 2} is goal ^ s = 2); several
+      // chains per wave: the plain form, which the compiler turns into
+      // selects (each form measured the faster one for its segment width).
+      if constexpr (LC == 64) {
+        if (prio > 0 && prio == best) {
+          far_any |= (goal ^ s) == 2;
+          s = med3(goal, s - nd.d, s + nd.d);
+          idle = 0;
+          streak = 0;
+        }
+      } else if (prio > 0 && prio == best) {
         far_any |= abs(goal - s) == 2;
-        s = min(max(goal, s - nd.d), s + nd.d);  // towards the goal by at most d
+        s = min(max(goal, s - nd.d), s + nd.d);
         idle = 0;
         streak = 0;
       }
