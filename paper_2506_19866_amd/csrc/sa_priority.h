@@ -21,9 +21,10 @@
 //    per-node regulator masks (threshold 1 or any, w*p >= 1, = 2, <= -1, = -2).
 //
 // The highest priority of a step is a maximum over the segment: DPP within
-// rows of 16 lanes, then gfx950's row and half-wave swaps (v_permlane16_swap,
-// v_permlane32_swap).  Two more masks per node (sources with w != 0, and
-// whether an in-edge has p = +1 and w != 0) give the constraint count.
+// rows of 16 lanes, then gfx950's row swap (v_permlane16_swap) for a 32-lane
+// segment, or the DPP row broadcasts and one lane read for a whole wave.  Two
+// more masks per node (sources with w != 0, and whether an in-edge has p = +1
+// and w != 0) give the constraint count.
 #pragma once
 #include <climits>
 
